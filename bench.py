@@ -1,0 +1,280 @@
+"""Throughput benchmark of vktApplyFilter on one MI355X.
+
+Default workload: the plain-path pair of 512^3 volumes --
+  (a) uint8 CT-like phantom (N(40, 8^2) background, 200 solid spheres),
+      integer 3^3 box filter with divisor 27, clamp, uint8 out (bit-exact);
+  (b) float32 smoothed Gaussian noise (sigma 4), 5^3 Gaussian sigma 1.5,
+      clamp, float32 out.
+One step = one ApplyFilter of (a) and one of (b), with inputs resident in HBM.
+Prints ONE JSON line (metric Gvoxels/s = output cells / device time).
+
+Other workloads (--workload): c1 (64^3 float32, 3^3 Gaussian), c3a / c3b
+(1024^3 float32 blob field, dense 7^3 / 9^3 unit-L1 weights), c5 (2048 x 2048
+x 1024 uint16 ellipsoid phantom, 11^3 Gaussian sigma 2.5).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP32_VECTOR_PEAK_TF = 157.3    # MI355X FP32 vector (packed FMA), TFLOP/s
+BF16_MFMA_PEAK_TF = 2500.0     # MI355X dense bf16 matrix, TFLOP/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c2",
+                    choices=["c1", "c2", "c2a", "c2b", "c3a", "c3b", "c5"])
+    ap.add_argument("--precision", default="auto", choices=["auto", "fp32", "splitbf16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target CPU time of the oracle baseline sample")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration)")
+    return ap.parse_args()
+
+
+# --------------------------------------------------------------- workloads --
+
+def make_cases(name, device):
+    """List of dicts: name, src tensor, weights, divisor, flops/voxel, bytes."""
+    import numpy as np
+    import torch
+    from paper_2203_10213_amd import synth
+    S = synth.SEEDS
+    cases = []
+    if name in ("c2", "c2a"):
+        src = torch.from_numpy(synth.ct_phantom_u8(512, S["c2a"])).to(device)
+        w, D = synth.box_int(3)
+        cases.append(dict(name="c2a_u8_512_box3_div27", src=src, w=w, D=D, k=3))
+    if name in ("c2", "c2b"):
+        src = synth.smoothed_noise_f32(512, 4.0, S["c2b"], device=device)
+        cases.append(dict(name="c2b_f32_512_gauss5_s1.5", src=src,
+                          w=synth.gaussian_weights(5, 1.5), D=None, k=5))
+    if name == "c1":
+        src = torch.from_numpy(synth.uniform_f32((64, 64, 64), S["c1"])).to(device)
+        cases.append(dict(name="c1_f32_64_gauss3_s1", src=src,
+                          w=synth.gaussian_weights(3, 1.0), D=None, k=3))
+    if name in ("c3a", "c3b"):
+        k = 7 if name == "c3a" else 9
+        src = synth.blob_field_f32(1024, 64, S["c3"], device=device)
+        w = synth.random_l1(k, S["c3a_w"] if k == 7 else S["c3b_w"])
+        cases.append(dict(name=f"{name}_f32_1024_dense{k}_l1", src=src, w=w, D=None, k=k))
+    if name == "c5":
+        src = synth.ellipsoid_phantom_u16((1024, 2048, 2048), 5000, S["c5"], device=device)
+        cases.append(dict(name="c5_u16_2048x2048x1024_gauss11_s2.5", src=src,
+                          w=synth.gaussian_weights(11, 2.5), D=None, k=11))
+    for c in cases:
+        c["voxels"] = c["src"].numel()
+        c["cell_bytes"] = c["src"].element_size()
+        c["flops_per_voxel"] = 2 * c["k"] ** 3
+    return cases
+
+
+def kernel_source_sha():
+    """Hash of the HIP sources; profile-derived traffic is only reported for
+    the kernels it was measured on."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2203_10213_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(case_name):
+    """HBM bytes per launch from committed rocprofv3 --pmc summaries, scaled
+    by the copy-kernel calibration, if they match the current kernels."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+        e = d.get(case_name)
+        if e and e.get("kernel_src_sha") == kernel_source_sha():
+            return e["hbm_bytes_per_launch"]
+    except (ValueError, KeyError):
+        pass
+    return None
+
+
+# ------------------------------------------------------------ CPU baseline --
+
+def cpu_baseline(cases, target_s):
+    """The FP64 oracle timed on this host's cores on a bounded z-slab of each
+    case (same planes count fraction for every case), scaled to Gvoxels/s of
+    the whole step's mix."""
+    import numpy as np
+    import oracle
+    nthreads = min(16, os.cpu_count() or 1)
+    # calibrate with one plane per case, then size the slab to ~target_s
+    per_plane = []
+    hosts = []
+    for c in cases:
+        src = c["src"].cpu().numpy()
+        hosts.append(src)
+        t0 = time.perf_counter()
+        oracle.correlate(src, np.asarray(c["w"], np.float64), "clamp", z_range=(0, 1),
+                         nthreads=nthreads, with_abs=False)
+        per_plane.append(time.perf_counter() - t0)
+    nplanes = max(1, int(target_s / max(sum(per_plane), 1e-6)))
+    tot_vox, tot_t = 0, 0.0
+    for c, src in zip(cases, hosts):
+        Z = src.shape[0]
+        z0 = Z // 2
+        z1 = min(Z, z0 + nplanes)
+        t0 = time.perf_counter()
+        oracle.correlate(src, np.asarray(c["w"], np.float64), "clamp", z_range=(z0, z1),
+                         nthreads=nthreads, with_abs=False)
+        dt = time.perf_counter() - t0
+        # weight each case by its share of the step's voxels
+        frac = c["voxels"] / (src.shape[1] * src.shape[2] * (z1 - z0))
+        tot_vox += c["voxels"]
+        tot_t += dt * frac
+    return {"value": tot_vox / tot_t / 1e9, "unit": "Gvoxels/s", "cores": nthreads,
+            "kind": "oracle",
+            "sample": f"FP64 direct-sum oracle on {nplanes} middle z-planes of each case "
+                      f"({', '.join(c['name'] for c in cases)}), {nthreads} threads, "
+                      f"time scaled to the full volumes"}
+
+
+# -------------------------------------------------------------------- main --
+
+def copy_probe():
+    import torch
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n, "launches": 3}))
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(a single volume would shard along z with an r-plane halo exchange)",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2203_10213_amd import vkt
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    if args.copy_probe:
+        copy_probe()
+        return
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    print(f"[bench] building inputs for {args.workload}", file=sys.stderr, flush=True)
+    cases = make_cases(args.workload, dev)
+    stream = torch.cuda.current_stream()
+    vkt.vktSetStream(stream)
+    vkt.vktSetPrecision(args.precision)
+    for c in cases:
+        c["dst"] = torch.empty_like(c["src"])
+        c["hs"] = vkt.volume_from_tensor(c["src"])
+        c["hd"] = vkt.volume_from_tensor(c["dst"])
+        c["hf"] = (vkt.vktFilterCreate(c["w"]) if c["D"] is None
+                   else vkt.vktFilterCreateInt(c["w"], c["D"]))
+    torch.cuda.synchronize()
+
+    def step(evs=None):
+        for i, c in enumerate(cases):
+            if evs is not None:
+                evs[i][0].record(stream)
+            vkt.vktApplyFilter(c["hd"], c["hs"], c["hf"], vkt.vktAddressModeClamp)
+            if evs is not None:
+                evs[i][1].record(stream)
+
+    print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    vkt.vktSynchronize()
+    torch.cuda.synchronize()
+
+    K = args.steps
+    evs = [[[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in cases]
+           for _ in range(K)]
+    t_begin = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_begin.record(stream)
+    for s in range(K):
+        step(evs[s])
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    vkt.vktSynchronize()
+    total_ms = t_begin.elapsed_time(t_end)
+    ms_step = total_ms / K
+    voxels = sum(c["voxels"] for c in cases)
+    value = voxels / (ms_step * 1e-3) / 1e9
+
+    per_case = []
+    for i, c in enumerate(cases):
+        ms = sum(evs[s][i][0].elapsed_time(evs[s][i][1]) for s in range(K)) / K
+        bytes_alg = 2 * c["voxels"] * c["cell_bytes"]
+        flops = c["voxels"] * c["flops_per_voxel"]
+        gbs = bytes_alg / (ms * 1e-3) / 1e9
+        tfs = flops / (ms * 1e-3) / 1e12
+        per_case.append(dict(case=c["name"], ms=ms, gvoxels_s=c["voxels"] / (ms * 1e-3) / 1e9,
+                             hbm_gbs=gbs, hbm_frac=gbs / HBM_PEAK_GBS,
+                             fp32_tflops=tfs, fp32_frac=tfs / FP32_VECTOR_PEAK_TF,
+                             algorithmic_bytes=bytes_alg, flops=flops))
+    dom = max(range(len(cases)), key=lambda i: per_case[i]["ms"])
+    d = per_case[dom]
+    # bound: whichever roofline the algorithmic work hits first
+    t_hbm = d["algorithmic_bytes"] / (HBM_PEAK_GBS * 1e9)
+    t_alu = d["flops"] / (FP32_VECTOR_PEAK_TF * 1e12)
+    if t_hbm >= t_alu:
+        roof = {"bound": "hbm", "achieved": d["hbm_gbs"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": d["hbm_frac"]}
+    else:
+        roof = {"bound": "alu", "achieved": d["fp32_tflops"], "peak": FP32_VECTOR_PEAK_TF,
+                "unit": "TFLOP/s", "frac": d["fp32_frac"]}
+    roof["kernel_case"] = d["case"]
+    roof["traffic"] = stored_traffic(d["case"])
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle baseline", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(cases, args.cpu_seconds)
+
+    dtype = {torch.uint8: "u8", torch.uint16: "u16", torch.float32: "f32"}
+    line = {
+        "metric": "Gvoxels/s ApplyFilter on 1 MI355X",
+        "value": value, "unit": "Gvoxels/s", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "+".join(sorted({"f32" if c["D"] is None else "int32" for c in cases})),
+        "data": "synthetic",
+        "config": {"workload": args.workload,
+                   "cases": [f"{c['name']} ({dtype[c['src'].dtype]} "
+                             f"{'x'.join(str(v) for v in reversed(c['src'].shape))})"
+                             for c in cases],
+                   "address_mode": "clamp", "precision": args.precision},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "per_case": per_case,
+    }
+    for c in cases:
+        vkt.vktFilterDestroy(c["hf"])
+        vkt.vktStructuredVolumeDestroy(c["hs"])
+        vkt.vktStructuredVolumeDestroy(c["hd"])
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,175 @@
+/*
+ * vkt.h -- C99 interface of libvkt, an MI355X (gfx950) implementation of the
+ * structured-volume ApplyFilter path of volkit (Zellmann, Aguirre, Schulze,
+ * "Volkit: A Performance-Portable Computer Vision Library for 3D Volumetric
+ * Data").
+ *
+ * Style follows the paper's C99 API (Sec. 3.3 and Fig. 4): a `vkt` prefix,
+ * handle out-parameters, a structured volume made of dims, a cell format, a
+ * cell size and a value range.  All calls return a vktError; no C++ exception
+ * crosses this interface.
+ *
+ * Volume layout (device memory): dense, x fastest,
+ *     index(x, y, z) = x + dimX * (y + dimY * z),
+ * cells of 1 (UInt8), 2 (UInt16) or 4 (Float32) bytes.
+ *
+ * Execution model (paper Sec. 3.1, thread-local ExecutionPolicy): every call
+ * enqueues its work on the calling thread's HIP stream (vktSetStream; default
+ * the null stream of the current device) and returns after the enqueue.
+ * Argument errors are reported synchronously, before anything is enqueued,
+ * and leave every output untouched.  Faults of enqueued work surface as
+ * vktDeviceError from vktSynchronize or from a later call.
+ */
+#ifndef VKT_H
+#define VKT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum vktError {
+    vktNoError = 0,
+    vktInvalidValue = 1,   /* bad handle, pointer, size or combination */
+    vktOutOfMemory = 2,    /* device allocation failed */
+    vktDeviceError = 3,    /* a HIP call or an enqueued kernel failed */
+    vktUnsupported = 4     /* valid request that this library cannot run */
+} vktError;
+
+typedef enum vktDataFormat {
+    vktDataFormatUInt8 = 0,
+    vktDataFormatUInt16 = 1,
+    vktDataFormatFloat32 = 2
+} vktDataFormat;
+
+/* Boundary rule for filter taps that fall outside the volume. */
+typedef enum vktAddressMode {
+    vktAddressModeClamp = 0,   /* nearest edge cell */
+    vktAddressModeWrap = 1,    /* periodic */
+    vktAddressModeMirror = 2,  /* reflect about the cell edge (edge repeated) */
+    vktAddressModeBorder = 3   /* zero outside */
+} vktAddressMode;
+
+/* Arithmetic used by vktApplyFilter on the calling thread. */
+typedef enum vktPrecision {
+    vktPrecisionAuto = 0,      /* library chooses per call */
+    vktPrecisionFP32 = 1,      /* FP32 multiply-add on the vector ALUs */
+    vktPrecisionSplitBF16 = 2  /* bf16 matrix cores, split operands, FP32 sums */
+} vktPrecision;
+
+typedef struct vktStructuredVolume_* vktStructuredVolume;
+typedef struct vktFilter_* vktFilter;
+
+/* ---- structured volumes (paper Sec. 3.2 "Volume Types", Fig. 4) -------- */
+
+/* Create a volume that owns a zero-filled device buffer of dimX*dimY*dimZ
+ * cells on the current device.  cellX/Y/Z is the cell size (metadata).
+ * [lo, hi] is the value range that Fill/FillRange map float values through
+ * for integer formats (lo != hi required for UInt8/UInt16).
+ * Errors: vktInvalidValue for a NULL out-pointer, a dim <= 0, an unknown
+ * format or lo == hi on an integer format; vktOutOfMemory. */
+vktError vktStructuredVolumeCreate(vktStructuredVolume* volume, int32_t dimX,
+                                   int32_t dimY, int32_t dimZ,
+                                   vktDataFormat format, float cellX,
+                                   float cellY, float cellZ, float lo, float hi);
+
+/* Wrap caller-owned device memory (e.g. a torch tensor) without copying.
+ * The library never frees devPtr; the caller keeps it alive until
+ * vktStructuredVolumeDestroy has returned and all enqueued work using it has
+ * completed.  devPtr must be aligned to the cell size.
+ * Errors: as vktStructuredVolumeCreate, plus a NULL or misaligned devPtr. */
+vktError vktStructuredVolumeCreateFromDevicePtr(vktStructuredVolume* volume,
+                                                int32_t dimX, int32_t dimY,
+                                                int32_t dimZ,
+                                                vktDataFormat format,
+                                                void* devPtr, float lo,
+                                                float hi);
+
+/* Release the handle; frees the buffer only if the volume owns it.  The
+ * buffer is freed with hipFree, which waits for outstanding work on it. */
+vktError vktStructuredVolumeDestroy(vktStructuredVolume volume);
+
+vktError vktStructuredVolumeGetDevicePtr(vktStructuredVolume volume,
+                                         void** devPtr);
+vktError vktStructuredVolumeGetDims(vktStructuredVolume volume, int32_t* dimX,
+                                    int32_t* dimY, int32_t* dimZ);
+vktError vktStructuredVolumeGetDataFormat(vktStructuredVolume volume,
+                                          vktDataFormat* format);
+
+/* ---- filters ------------------------------------------------------------ */
+
+/* A dense k*k*k filter of float weights, copied at creation (host array of
+ * k^3 floats, a fastest: w[a + k*(b + k*c)] multiplies the cell at offset
+ * (a-r, b-r, c-r), r = (k-1)/2 -- correlation orientation).
+ * Errors: vktInvalidValue for NULL pointers or k not odd in [1, 15];
+ * vktOutOfMemory. */
+vktError vktFilterCreate(vktFilter* filter, int32_t k, const float* weights);
+
+/* A dense k*k*k filter of integer weights with a divisor: the result is
+ * sum(w*s) / divisor, rounded half-up and saturated for integer formats
+ * (computed exactly).  |w| < 2^23, divisor in [1, 2^29].
+ * Errors: vktInvalidValue for NULL pointers, k not odd in [1, 15], a weight
+ * out of range or a divisor out of range; vktOutOfMemory. */
+vktError vktFilterCreateInt(vktFilter* filter, int32_t k, const int32_t* weights,
+                            int32_t divisor);
+
+vktError vktFilterDestroy(vktFilter filter);
+
+/* ---- Fill / FillRange (paper Sec. 3.2 "Volume Manipulation", Fig. 4) ---- */
+
+/* Set every cell to `value`.  Integer formats store
+ * clamp(floor((value - lo) / (hi - lo) * max + 1/2), 0, max); Float32 stores
+ * value.  Errors: vktInvalidValue for a bad handle. */
+vktError vktFill(vktStructuredVolume volume, float value);
+
+/* Set the cells of the half-open region [first, last) (cell coordinates) to
+ * `value`, mapped as in vktFill.  An empty region is a no-op.
+ * Errors: vktInvalidValue for a bad handle, first > last on an axis, or a
+ * region outside the volume. */
+vktError vktFillRange(vktStructuredVolume volume, int32_t firstX,
+                      int32_t firstY, int32_t firstZ, int32_t lastX,
+                      int32_t lastY, int32_t lastZ, float value);
+
+/* The paper's C99 names (Fig. 4); identical to vktFill / vktFillRange. */
+vktError vktFillSV(vktStructuredVolume volume, float value);
+vktError vktFillRangeSV(vktStructuredVolume volume, int32_t firstX,
+                        int32_t firstY, int32_t firstZ, int32_t lastX,
+                        int32_t lastY, int32_t lastZ, float value);
+
+/* ---- ApplyFilter (paper Sec. 3.2 "Volume Manipulation", Sec. 4.3) ------- */
+
+/* dst(x,y,z) = sum_{a,b,c} w[a + k(b + k c)] * src(A(x+a-r), A(y+b-r),
+ * A(z+c-r)) for every cell, with A the address mode on each axis, then
+ * stored in the volumes' format: Float32 as the FP32 result; UInt8/UInt16
+ * rounded half-up (floor(q + 1/2)) and saturated; integer-weight filters on
+ * integer formats compute floor((2T + D) / (2D)) exactly.
+ * dst and src must have equal dims and format and must not overlap.
+ * The arithmetic follows the thread's vktPrecision: FP32 runs on the vector
+ * ALUs; SplitBF16 (and Auto for k >= 5 on float weights) runs on bf16 matrix
+ * cores with split operands and FP32 accumulation.  Integer-weight filters
+ * always use exact integer arithmetic.
+ * Errors: vktInvalidValue for bad handles, mismatched or overlapping volumes
+ * or a mode out of range; vktUnsupported when an integer-weight filter's
+ * sum |w| * max(format) would exceed 2^30 or a plane exceeds 2^31 cells. */
+vktError vktApplyFilter(vktStructuredVolume dst, vktStructuredVolume src,
+                        vktFilter filter, vktAddressMode mode);
+
+/* ---- per-thread execution state (paper Sec. 3.1 ExecutionPolicy) -------- */
+
+/* stream is a hipStream_t (NULL = the default stream). */
+vktError vktSetStream(void* stream);
+vktError vktGetStream(void** stream);
+vktError vktSetPrecision(vktPrecision precision);
+vktError vktGetPrecision(vktPrecision* precision);
+
+/* Wait for the calling thread's stream; reports faults of enqueued work. */
+vktError vktSynchronize(void);
+
+const char* vktGetErrorString(vktError error);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VKT_H */

@@ -1,0 +1,403 @@
+// vkt_api.hip -- the C interface of libvkt (include/vkt.h): handles,
+// argument validation, the per-thread execution state and kernel dispatch.
+//
+// The per-thread state mirrors the paper's thread-local ExecutionPolicy
+// (Sec. 3.1): the stream work is enqueued on and the arithmetic precision.
+// Volumes are device resident; there is no implicit host<->device migration.
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <unordered_set>
+#include <vector>
+
+#include "vkt_internal.h"
+
+struct vktStructuredVolume_ {
+    int32_t dims[3];
+    vktDataFormat fmt;
+    float cell[3];
+    float lo, hi;
+    void* dev;
+    bool owned;
+    int device;
+};
+
+struct vktFilter_ {
+    int32_t k;
+    bool is_int;
+    int32_t divisor;
+    int64_t sum_abs_int;        // sum |w| for integer filters
+    float* d_wf;                // device float weights (k^3)
+    int32_t* d_wi;              // device int weights (k^3), integer filters
+    int device;
+};
+
+namespace {
+
+struct ThreadState {
+    hipStream_t stream = nullptr;
+    vktPrecision precision = vktPrecisionAuto;
+    bool init = false;
+};
+thread_local ThreadState t_state;
+
+ThreadState& state()
+{
+    if (!t_state.init) {
+        t_state.init = true;
+        if (const char* p = std::getenv("VKT_PRECISION")) {
+            if (!std::strcmp(p, "fp32")) t_state.precision = vktPrecisionFP32;
+            else if (!std::strcmp(p, "splitbf16")) t_state.precision = vktPrecisionSplitBF16;
+        }
+    }
+    return t_state;
+}
+
+// Live handles, so that stale or foreign handles are rejected instead of
+// dereferenced.
+std::mutex g_mu;
+std::unordered_set<const void*> g_volumes, g_filters;
+
+bool live_volume(const vktStructuredVolume_* v)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    return v && g_volumes.count(v);
+}
+bool live_filter(const vktFilter_* f)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    return f && g_filters.count(f);
+}
+
+vktError from_hip(hipError_t e)
+{
+    if (e == hipSuccess) return vktNoError;
+    if (e == hipErrorOutOfMemory) return vktOutOfMemory;
+    return vktDeviceError;
+}
+
+bool valid_format(int f) { return f >= vktDataFormatUInt8 && f <= vktDataFormatFloat32; }
+
+int64_t cells(const vktStructuredVolume_* v)
+{
+    return (int64_t)v->dims[0] * v->dims[1] * v->dims[2];
+}
+
+// Raw stored value for Fill: integer formats map [lo, hi] onto [0, max] with
+// half-up rounding and saturation; Float32 stores the value.
+uint32_t raw_fill_bits(const vktStructuredVolume_* v, float value)
+{
+    if (v->fmt == vktDataFormatFloat32) {
+        uint32_t u;
+        std::memcpy(&u, &value, 4);
+        return u;
+    }
+    const double mx = v->fmt == vktDataFormatUInt8 ? 255.0 : 65535.0;
+    double r = std::floor(((double)value - v->lo) / ((double)v->hi - v->lo) * mx + 0.5);
+    if (!(r >= 0.0)) r = 0.0;  // also maps NaN to 0
+    if (r > mx) r = mx;
+    return (uint32_t)r;
+}
+
+vktError create_volume(vktStructuredVolume* out, int32_t dx, int32_t dy, int32_t dz,
+                       vktDataFormat f, void* dev, bool own, const float cell[3],
+                       float lo, float hi)
+{
+    if (!out || dx <= 0 || dy <= 0 || dz <= 0 || !valid_format(f)) return vktInvalidValue;
+    if (f != vktDataFormatFloat32 && !(lo != hi)) return vktInvalidValue;
+    const int64_t n = (int64_t)dx * dy * dz;
+    const size_t bytes = (size_t)n * vkt::cell_bytes(f);
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return vktDeviceError;
+    if (own) {
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) return from_hip(e);
+        e = hipMemsetAsync(p, 0, bytes, state().stream);
+        if (e != hipSuccess) { (void)hipFree(p); return from_hip(e); }
+        dev = p;
+    }
+    auto* v = new (std::nothrow) vktStructuredVolume_{{dx, dy, dz}, f,
+                                                      {cell[0], cell[1], cell[2]},
+                                                      lo, hi, dev, own, device};
+    if (!v) {
+        if (own) (void)hipFree(dev);
+        return vktOutOfMemory;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_volumes.insert(v);
+    }
+    *out = v;
+    return vktNoError;
+}
+
+vktError create_filter(vktFilter* out, int32_t k, const float* wf, const int32_t* wi,
+                       int32_t divisor)
+{
+    if (!out || (!wf && !wi) || k < 1 || k > 15 || (k % 2) == 0) return vktInvalidValue;
+    const int n = k * k * k;
+    std::vector<float> hf(n);
+    std::vector<int32_t> hi;
+    int64_t sum_abs = 0;
+    if (wi) {
+        if (divisor < 1 || divisor > (1 << 29)) return vktInvalidValue;
+        hi.assign(wi, wi + n);
+        for (int i = 0; i < n; ++i) {
+            if (hi[i] <= -(1 << 23) || hi[i] >= (1 << 23)) return vktInvalidValue;
+            sum_abs += hi[i] < 0 ? -(int64_t)hi[i] : hi[i];
+            hf[i] = (float)hi[i];  // exact below 2^24
+        }
+    } else {
+        std::memcpy(hf.data(), wf, n * sizeof(float));
+    }
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return vktDeviceError;
+    float* dwf = nullptr;
+    int32_t* dwi = nullptr;
+    hipError_t e = hipMalloc(&dwf, n * sizeof(float));
+    if (e == hipSuccess) e = hipMemcpy(dwf, hf.data(), n * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess && wi) {
+        e = hipMalloc(&dwi, n * sizeof(int32_t));
+        if (e == hipSuccess)
+            e = hipMemcpy(dwi, hi.data(), n * sizeof(int32_t), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        if (dwf) (void)hipFree(dwf);
+        if (dwi) (void)hipFree(dwi);
+        return from_hip(e);
+    }
+    auto* f = new (std::nothrow) vktFilter_{k, wi != nullptr, wi ? divisor : 1, sum_abs,
+                                            dwf, dwi, device};
+    if (!f) {
+        (void)hipFree(dwf);
+        if (dwi) (void)hipFree(dwi);
+        return vktOutOfMemory;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_filters.insert(f);
+    }
+    *out = f;
+    return vktNoError;
+}
+
+}  // namespace
+
+namespace vkt {
+
+UDiv make_udiv(uint32_t d)
+{
+    uint32_t l = 0;
+    while (l < 32 && (uint64_t(1) << l) < d) ++l;  // l = ceil(log2 d)
+    const uint64_t m = ((uint64_t(1) << 32) * ((uint64_t(1) << l) - d)) / d + 1;
+    UDiv r;
+    r.m = (uint32_t)m;
+    r.sh1 = l < 1 ? l : 1;
+    r.sh2 = l > 1 ? l - 1 : 0;
+    return r;
+}
+
+}  // namespace vkt
+
+extern "C" {
+
+vktError vktStructuredVolumeCreate(vktStructuredVolume* volume, int32_t dimX,
+                                   int32_t dimY, int32_t dimZ, vktDataFormat format,
+                                   float cellX, float cellY, float cellZ, float lo,
+                                   float hi)
+{
+    const float cell[3] = {cellX, cellY, cellZ};
+    return create_volume(volume, dimX, dimY, dimZ, format, nullptr, true, cell, lo, hi);
+}
+
+vktError vktStructuredVolumeCreateFromDevicePtr(vktStructuredVolume* volume, int32_t dimX,
+                                                int32_t dimY, int32_t dimZ,
+                                                vktDataFormat format, void* devPtr,
+                                                float lo, float hi)
+{
+    if (!devPtr || !valid_format(format)) return vktInvalidValue;
+    if (reinterpret_cast<uintptr_t>(devPtr) % vkt::cell_bytes(format)) return vktInvalidValue;
+    const float cell[3] = {1.f, 1.f, 1.f};
+    return create_volume(volume, dimX, dimY, dimZ, format, devPtr, false, cell, lo, hi);
+}
+
+vktError vktStructuredVolumeDestroy(vktStructuredVolume v)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (!v || !g_volumes.erase(v)) return vktInvalidValue;
+    }
+    hipError_t e = hipSuccess;
+    if (v->owned) e = hipFree(v->dev);
+    delete v;
+    return from_hip(e);
+}
+
+vktError vktStructuredVolumeGetDevicePtr(vktStructuredVolume v, void** p)
+{
+    if (!live_volume(v) || !p) return vktInvalidValue;
+    *p = v->dev;
+    return vktNoError;
+}
+
+vktError vktStructuredVolumeGetDims(vktStructuredVolume v, int32_t* dx, int32_t* dy,
+                                    int32_t* dz)
+{
+    if (!live_volume(v) || !dx || !dy || !dz) return vktInvalidValue;
+    *dx = v->dims[0];
+    *dy = v->dims[1];
+    *dz = v->dims[2];
+    return vktNoError;
+}
+
+vktError vktStructuredVolumeGetDataFormat(vktStructuredVolume v, vktDataFormat* f)
+{
+    if (!live_volume(v) || !f) return vktInvalidValue;
+    *f = v->fmt;
+    return vktNoError;
+}
+
+vktError vktFilterCreate(vktFilter* filter, int32_t k, const float* weights)
+{
+    if (!weights) return vktInvalidValue;
+    return create_filter(filter, k, weights, nullptr, 1);
+}
+
+vktError vktFilterCreateInt(vktFilter* filter, int32_t k, const int32_t* weights,
+                            int32_t divisor)
+{
+    if (!weights) return vktInvalidValue;
+    return create_filter(filter, k, nullptr, weights, divisor);
+}
+
+vktError vktFilterDestroy(vktFilter f)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (!f || !g_filters.erase(f)) return vktInvalidValue;
+    }
+    hipError_t e = hipFree(f->d_wf);
+    if (f->d_wi) {
+        hipError_t e2 = hipFree(f->d_wi);
+        if (e == hipSuccess) e = e2;
+    }
+    delete f;
+    return from_hip(e);
+}
+
+vktError vktFill(vktStructuredVolume v, float value)
+{
+    if (!live_volume(v)) return vktInvalidValue;
+    return from_hip(vkt::launch_fill(v->dev, vkt::cell_bytes(v->fmt), cells(v),
+                                     raw_fill_bits(v, value), state().stream));
+}
+
+vktError vktFillRange(vktStructuredVolume v, int32_t x0, int32_t y0, int32_t z0,
+                      int32_t x1, int32_t y1, int32_t z1, float value)
+{
+    if (!live_volume(v)) return vktInvalidValue;
+    const int32_t first[3] = {x0, y0, z0}, last[3] = {x1, y1, z1};
+    for (int a = 0; a < 3; ++a)
+        if (first[a] < 0 || last[a] > v->dims[a] || first[a] > last[a]) return vktInvalidValue;
+    return from_hip(vkt::launch_fill_range(v->dev, vkt::cell_bytes(v->fmt), v->dims[0],
+                                           v->dims[1], first, last, raw_fill_bits(v, value),
+                                           state().stream));
+}
+
+vktError vktFillSV(vktStructuredVolume v, float value) { return vktFill(v, value); }
+
+vktError vktFillRangeSV(vktStructuredVolume v, int32_t x0, int32_t y0, int32_t z0,
+                        int32_t x1, int32_t y1, int32_t z1, float value)
+{
+    return vktFillRange(v, x0, y0, z0, x1, y1, z1, value);
+}
+
+vktError vktApplyFilter(vktStructuredVolume dst, vktStructuredVolume src, vktFilter filt,
+                        vktAddressMode mode)
+{
+    if (!live_volume(dst) || !live_volume(src) || !live_filter(filt)) return vktInvalidValue;
+    if (mode < vktAddressModeClamp || mode > vktAddressModeBorder) return vktInvalidValue;
+    if (dst->fmt != src->fmt) return vktInvalidValue;
+    for (int a = 0; a < 3; ++a)
+        if (dst->dims[a] != src->dims[a]) return vktInvalidValue;
+    const int64_t bytes = cells(src) * vkt::cell_bytes(src->fmt);
+    const char* d0 = static_cast<const char*>(dst->dev);
+    const char* s0 = static_cast<const char*>(src->dev);
+    if (d0 < s0 + bytes && s0 < d0 + bytes) return vktInvalidValue;  // overlap
+    if ((int64_t)src->dims[0] * src->dims[1] >= (int64_t(1) << 31)) return vktUnsupported;
+
+    vkt::FilterJob j{};
+    j.src = src->dev;
+    j.dst = dst->dev;
+    j.X = src->dims[0];
+    j.Y = src->dims[1];
+    j.Z = src->dims[2];
+    j.mode = mode;
+    j.fmt = src->fmt;
+    j.k = filt->k;
+    j.wf = filt->d_wf;
+    j.wi = filt->d_wi;
+    j.int_filter = filt->is_int;
+    j.D = filt->divisor;
+    j.inv_D = 1.0f / (float)filt->divisor;
+    j.int_acc = false;
+    if (filt->is_int && src->fmt != vktDataFormatFloat32) {
+        const int64_t mx = src->fmt == vktDataFormatUInt8 ? 255 : 65535;
+        if (filt->sum_abs_int * mx > (int64_t(1) << 30)) return vktUnsupported;
+        j.int_acc = true;
+        j.div2D = vkt::make_udiv(2u * (uint32_t)filt->divisor);
+    }
+    j.vec_store = (j.X % 4 == 0) &&
+                  (reinterpret_cast<uintptr_t>(dst->dev) % (4 * vkt::cell_bytes(src->fmt)) == 0);
+    return from_hip(vkt::launch_filter_valu(j, state().stream));
+}
+
+vktError vktSetStream(void* stream)
+{
+    state().stream = static_cast<hipStream_t>(stream);
+    return vktNoError;
+}
+
+vktError vktGetStream(void** stream)
+{
+    if (!stream) return vktInvalidValue;
+    *stream = state().stream;
+    return vktNoError;
+}
+
+vktError vktSetPrecision(vktPrecision p)
+{
+    if (p < vktPrecisionAuto || p > vktPrecisionSplitBF16) return vktInvalidValue;
+    state().precision = p;
+    return vktNoError;
+}
+
+vktError vktGetPrecision(vktPrecision* p)
+{
+    if (!p) return vktInvalidValue;
+    *p = state().precision;
+    return vktNoError;
+}
+
+vktError vktSynchronize(void)
+{
+    hipError_t e = hipStreamSynchronize(state().stream);
+    if (e == hipSuccess) e = hipGetLastError();
+    return from_hip(e);
+}
+
+const char* vktGetErrorString(vktError e)
+{
+    switch (e) {
+    case vktNoError: return "no error";
+    case vktInvalidValue: return "invalid value";
+    case vktOutOfMemory: return "out of device memory";
+    case vktDeviceError: return "device error";
+    case vktUnsupported: return "unsupported";
+    }
+    return "unknown error";
+}
+
+}  // extern "C"

@@ -1,0 +1,251 @@
+"""Python binding of libvkt (include/vkt.h): argument marshalling only.
+
+Every call goes through the C interface of the in-tree libvkt.so; all volume
+arithmetic runs in its HIP kernels.  torch supplies device memory (tensors)
+and streams.  There is no fallback: if libvkt.so is missing, or no GPU is
+visible when a call needs one, the call raises.
+
+The function names are the C names.  Handles are opaque integers.
+"""
+import ctypes
+import os
+
+import torch  # loads torch's HIP runtime first; libvkt then binds to it
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvkt.so")
+
+# enums of include/vkt.h
+vktNoError, vktInvalidValue, vktOutOfMemory, vktDeviceError, vktUnsupported = range(5)
+vktDataFormatUInt8, vktDataFormatUInt16, vktDataFormatFloat32 = range(3)
+vktAddressModeClamp, vktAddressModeWrap, vktAddressModeMirror, vktAddressModeBorder = range(4)
+vktPrecisionAuto, vktPrecisionFP32, vktPrecisionSplitBF16 = range(3)
+
+MODES = {"clamp": vktAddressModeClamp, "wrap": vktAddressModeWrap,
+         "mirror": vktAddressModeMirror, "border": vktAddressModeBorder}
+PRECISIONS = {"auto": vktPrecisionAuto, "fp32": vktPrecisionFP32,
+              "splitbf16": vktPrecisionSplitBF16}
+TORCH_FORMAT = {torch.uint8: vktDataFormatUInt8, torch.uint16: vktDataFormatUInt16,
+                torch.float32: vktDataFormatFloat32}
+
+# Every function include/vkt.h declares, with its argument types.
+_P, _I32, _F = ctypes.c_void_p, ctypes.c_int32, ctypes.c_float
+_PP = ctypes.POINTER(ctypes.c_void_p)
+_PI = ctypes.POINTER(ctypes.c_int32)
+SIGNATURES = {
+    "vktStructuredVolumeCreate": [_PP, _I32, _I32, _I32, ctypes.c_int, _F, _F, _F, _F, _F],
+    "vktStructuredVolumeCreateFromDevicePtr": [_PP, _I32, _I32, _I32, ctypes.c_int, _P, _F, _F],
+    "vktStructuredVolumeDestroy": [_P],
+    "vktStructuredVolumeGetDevicePtr": [_P, _PP],
+    "vktStructuredVolumeGetDims": [_P, _PI, _PI, _PI],
+    "vktStructuredVolumeGetDataFormat": [_P, ctypes.POINTER(ctypes.c_int)],
+    "vktFilterCreate": [_PP, _I32, ctypes.POINTER(ctypes.c_float)],
+    "vktFilterCreateInt": [_PP, _I32, _PI, _I32],
+    "vktFilterDestroy": [_P],
+    "vktFill": [_P, _F],
+    "vktFillRange": [_P, _I32, _I32, _I32, _I32, _I32, _I32, _F],
+    "vktFillSV": [_P, _F],
+    "vktFillRangeSV": [_P, _I32, _I32, _I32, _I32, _I32, _I32, _F],
+    "vktApplyFilter": [_P, _P, _P, ctypes.c_int],
+    "vktSetStream": [_P],
+    "vktGetStream": [_PP],
+    "vktSetPrecision": [ctypes.c_int],
+    "vktGetPrecision": [ctypes.POINTER(ctypes.c_int)],
+    "vktSynchronize": [],
+    "vktGetErrorString": [ctypes.c_int],
+}
+
+
+class VktError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: {error_string(code)} ({code})")
+
+
+_lib = None
+
+
+def lib():
+    """Load the in-tree libvkt.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_char_p if name == "vktGetErrorString" else ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def error_string(code):
+    return lib().vktGetErrorString(int(code)).decode()
+
+
+def _ok(code, where):
+    if code != vktNoError:
+        raise VktError(code, where)
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        raise RuntimeError("libvkt needs a visible GPU; none is available")
+
+
+# ------------------------------------------------------------------ volumes --
+
+def vktStructuredVolumeCreate(dims, fmt, cell=(1.0, 1.0, 1.0), lo=0.0, hi=1.0):
+    """Owned, zero-filled device volume; dims = (X, Y, Z)."""
+    _require_gpu()
+    h = ctypes.c_void_p()
+    _ok(lib().vktStructuredVolumeCreate(ctypes.byref(h), *[int(d) for d in dims],
+                                        int(fmt), *[float(c) for c in cell],
+                                        float(lo), float(hi)),
+        "vktStructuredVolumeCreate")
+    return h.value
+
+
+def vktStructuredVolumeCreateFromDevicePtr(dims, fmt, ptr, lo=0.0, hi=1.0):
+    h = ctypes.c_void_p()
+    _ok(lib().vktStructuredVolumeCreateFromDevicePtr(
+        ctypes.byref(h), *[int(d) for d in dims], int(fmt), ctypes.c_void_p(ptr),
+        float(lo), float(hi)), "vktStructuredVolumeCreateFromDevicePtr")
+    return h.value
+
+
+def vktStructuredVolumeDestroy(h):
+    _ok(lib().vktStructuredVolumeDestroy(h), "vktStructuredVolumeDestroy")
+
+
+def vktStructuredVolumeGetDevicePtr(h):
+    p = ctypes.c_void_p()
+    _ok(lib().vktStructuredVolumeGetDevicePtr(h, ctypes.byref(p)),
+        "vktStructuredVolumeGetDevicePtr")
+    return p.value
+
+
+def vktStructuredVolumeGetDims(h):
+    d = [ctypes.c_int32() for _ in range(3)]
+    _ok(lib().vktStructuredVolumeGetDims(h, *[ctypes.byref(v) for v in d]),
+        "vktStructuredVolumeGetDims")
+    return tuple(v.value for v in d)
+
+
+def vktStructuredVolumeGetDataFormat(h):
+    f = ctypes.c_int()
+    _ok(lib().vktStructuredVolumeGetDataFormat(h, ctypes.byref(f)),
+        "vktStructuredVolumeGetDataFormat")
+    return f.value
+
+
+# ------------------------------------------------------------------ filters --
+
+def vktFilterCreate(weights):
+    """weights: (k, k, k) array-like indexed [c, b, a]; copied as float32."""
+    import numpy as np
+    w = np.ascontiguousarray(weights, dtype=np.float32)
+    k = w.shape[0]
+    if w.shape != (k, k, k):
+        raise ValueError("filter must be k*k*k")
+    h = ctypes.c_void_p()
+    _ok(lib().vktFilterCreate(ctypes.byref(h), k,
+                              w.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+        "vktFilterCreate")
+    return h.value
+
+
+def vktFilterCreateInt(weights, divisor):
+    import numpy as np
+    w = np.ascontiguousarray(weights, dtype=np.int32)
+    k = w.shape[0]
+    if w.shape != (k, k, k):
+        raise ValueError("filter must be k*k*k")
+    h = ctypes.c_void_p()
+    _ok(lib().vktFilterCreateInt(ctypes.byref(h), k,
+                                 w.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                 int(divisor)), "vktFilterCreateInt")
+    return h.value
+
+
+def vktFilterDestroy(h):
+    _ok(lib().vktFilterDestroy(h), "vktFilterDestroy")
+
+
+# ------------------------------------------------------------- algorithms --
+
+def vktFill(vol, value):
+    _ok(lib().vktFill(vol, float(value)), "vktFill")
+
+
+def vktFillRange(vol, first, last, value):
+    _ok(lib().vktFillRange(vol, *[int(v) for v in first], *[int(v) for v in last],
+                           float(value)), "vktFillRange")
+
+
+vktFillSV = vktFill
+vktFillRangeSV = vktFillRange
+
+
+def vktApplyFilter(dst, src, filt, mode=vktAddressModeClamp):
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    _ok(lib().vktApplyFilter(dst, src, filt, m), "vktApplyFilter")
+
+
+# ------------------------------------------------------------- thread state --
+
+def vktSetStream(stream):
+    """stream: a torch.cuda.Stream, a raw hipStream_t integer, or None."""
+    if isinstance(stream, torch.cuda.Stream):
+        stream = stream.cuda_stream
+    _ok(lib().vktSetStream(ctypes.c_void_p(stream or None)), "vktSetStream")
+
+
+def vktGetStream():
+    p = ctypes.c_void_p()
+    _ok(lib().vktGetStream(ctypes.byref(p)), "vktGetStream")
+    return p.value
+
+
+def vktSetPrecision(p):
+    p = PRECISIONS[p] if isinstance(p, str) else int(p)
+    _ok(lib().vktSetPrecision(p), "vktSetPrecision")
+
+
+def vktGetPrecision():
+    p = ctypes.c_int()
+    _ok(lib().vktGetPrecision(ctypes.byref(p)), "vktGetPrecision")
+    return p.value
+
+
+def vktSynchronize():
+    _ok(lib().vktSynchronize(), "vktSynchronize")
+
+
+# ------------------------------------------------------ tensor conveniences --
+
+def volume_from_tensor(t, lo=0.0, hi=1.0):
+    """Borrowing handle for a contiguous (Z, Y, X) device tensor."""
+    if not t.is_cuda or not t.is_contiguous() or t.dim() != 3:
+        raise ValueError("need a contiguous 3-D device tensor")
+    if t.dtype not in TORCH_FORMAT:
+        raise ValueError(f"unsupported dtype {t.dtype}")
+    Z, Y, X = t.shape
+    return vktStructuredVolumeCreateFromDevicePtr((X, Y, Z), TORCH_FORMAT[t.dtype],
+                                                  t.data_ptr(), lo, hi)
+
+
+def apply_filter(dst, src, weights, mode="clamp", divisor=None):
+    """One ApplyFilter of src into dst (device tensors) on torch's current
+    stream; integer weights with `divisor` create an integer filter."""
+    vktSetStream(torch.cuda.current_stream())
+    hs = volume_from_tensor(src)
+    hd = volume_from_tensor(dst)
+    hf = vktFilterCreate(weights) if divisor is None else vktFilterCreateInt(weights, divisor)
+    try:
+        vktApplyFilter(hd, hs, hf, mode)
+    finally:
+        vktFilterDestroy(hf)
+        vktStructuredVolumeDestroy(hd)
+        vktStructuredVolumeDestroy(hs)

@@ -1,0 +1,92 @@
+"""Helpers shared by the GPU tests: run libvkt through its C interface on
+device tensors and compare with the FP64 oracle at the stated tolerances."""
+import os
+
+import numpy as np
+
+TOL_F32 = 1e-5      # |gpu - T| / sum|w||s| for float32 volumes
+ORACLE_THREADS = min(16, os.cpu_count() or 1)
+
+NP2TORCH = None
+
+
+def torch_dtype(np_dtype):
+    import torch
+    return {np.dtype(np.uint8): torch.uint8, np.dtype(np.uint16): torch.uint16,
+            np.dtype(np.float32): torch.float32}[np.dtype(np_dtype)]
+
+
+def to_device(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def sentinel_like(t):
+    """Output tensor pre-filled with a sentinel so unwritten cells show."""
+    import torch
+    out = torch.empty_like(t)
+    if out.dtype == torch.float32:
+        out.fill_(float("nan"))
+    elif out.dtype == torch.uint8:
+        out.fill_(0xA5)
+    else:
+        out.view(torch.int16).fill_(-23131)  # 0xA5A5
+    return out
+
+
+def run_filter(src_np, weights, mode="clamp", divisor=None, precision="auto",
+               src_t=None):
+    """ApplyFilter on the GPU through the C interface; returns numpy."""
+    import torch
+    from paper_2203_10213_amd import vkt
+    src = to_device(src_np) if src_t is None else src_t
+    dst = sentinel_like(src)
+    vkt.vktSetPrecision(precision)
+    vkt.apply_filter(dst, src, weights, mode, divisor)
+    vkt.vktSynchronize()
+    torch.cuda.synchronize()
+    return dst.cpu().numpy()
+
+
+def check_against_oracle(orc, src, w, mode, out, divisor=None, pts=None,
+                         tol=TOL_F32, what=""):
+    """Compare a GPU result with the oracle, on every cell or at pts."""
+    wd = np.asarray(w, np.float64)
+    if pts is None:
+        T, A = orc.correlate(src, wd, mode, nthreads=ORACLE_THREADS)
+        got = out
+    else:
+        T, A = orc.correlate_points(src, wd, mode, pts)
+        got = out[pts[:, 2], pts[:, 1], pts[:, 0]]
+    if src.dtype == np.float32:
+        q = T / divisor if divisor is not None else T
+        Ad = A / divisor if divisor is not None else A
+        err = np.abs(got.astype(np.float64) - q)
+        ok = np.where(Ad > 0, err <= tol * Ad, got == 0)
+        bad = np.argwhere(~ok)
+        assert bad.size == 0, (f"{what}: {len(bad)} cells exceed {tol} rel-to-sum|w||s|;"
+                               f" first {bad[:3].tolist()} max {np.max(err / np.maximum(Ad, 1e-300))}")
+        return float(np.max(np.where(Ad > 0, err / np.maximum(Ad, 1e-300), 0.0)))
+    if divisor is not None:
+        want = orc.store_int_filter(T, divisor, src.dtype)
+        diff = got.astype(np.int64) - want.astype(np.int64)
+        bad = np.argwhere(diff != 0)
+        assert bad.size == 0, f"{what}: {len(bad)} cells differ (bit-exact), first {bad[:3].tolist()}"
+        return 0.0
+    want = orc.store_float_filter(T, src.dtype)
+    diff = np.abs(got.astype(np.int64) - want.astype(np.int64))
+    assert diff.max(initial=0) <= 1, f"{what}: max LSB diff {diff.max()}"
+    return float(diff.max(initial=0))
+
+
+def sample_points(shape, n, seed, edges=True):
+    """n random cells plus the 8 corners and edge-adjacent cells."""
+    Z, Y, X = shape
+    g = np.random.default_rng(seed)
+    pts = [np.stack([g.integers(0, X, n), g.integers(0, Y, n), g.integers(0, Z, n)], 1)]
+    if edges:
+        cs = [(x, y, z) for x in (0, 1, X - 2, X - 1) for y in (0, 1, Y - 2, Y - 1)
+              for z in (0, 1, Z - 2, Z - 1)]
+        pts.append(np.array([[min(max(a, 0), X - 1), min(max(b, 0), Y - 1),
+                              min(max(c, 0), Z - 1)] for a, b, c in cs]))
+    return np.concatenate(pts).astype(np.int64)

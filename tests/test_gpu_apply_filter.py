@@ -1,0 +1,223 @@
+"""GPU parity of vktApplyFilter against the FP64 oracle.
+
+Tolerances: integer cells with integer weights are bit-exact (any divisor);
+integer cells with float weights are within 1 LSB; float32 cells are within
+1e-5 of sum |w||s| (plain relative error for non-negative filters and data).
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+from _gpu import (ORACLE_THREADS, check_against_oracle, run_filter,
+                  sample_points, sentinel_like, to_device)
+
+pytestmark = pytest.mark.gpu
+
+MODES = ["clamp", "wrap", "mirror", "border"]
+KS = [1, 3, 5, 7, 9, 11, 13, 15]
+
+
+def _vol(g, shape, dtype):
+    if dtype == np.float32:
+        return g.standard_normal(shape).astype(np.float32)
+    return g.integers(0, np.iinfo(dtype).max + 1, shape).astype(dtype)
+
+
+@pytest.fixture(autouse=True)
+def _fresh_precision():
+    from paper_2203_10213_amd import vkt
+    vkt.vktSetPrecision("auto")
+    yield
+    vkt.vktSetPrecision("auto")
+
+
+# Ragged shapes: several 64x32 tiles with tails, dims below the radius, and
+# single-cell axes.  (Z, Y, X)
+SHAPES = [(1, 1, 1), (3, 2, 1), (5, 1, 70), (9, 33, 65), (20, 40, 130), (7, 70, 3)]
+
+
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16, np.float32])
+@pytest.mark.parametrize("mode", MODES)
+def test_float_weights_sweep(orc, dtype, mode):
+    g = np.random.default_rng(100 + MODES.index(mode))
+    for shape in SHAPES:
+        for k in KS:
+            if np.prod(shape) * k ** 3 > 6e7:
+                continue
+            src = _vol(g, shape, dtype)
+            w = g.standard_normal((k, k, k)).astype(np.float32)
+            if dtype != np.float32:
+                w = np.abs(w) / np.abs(w).sum()  # keep integer results in range
+            out = run_filter(src, w, mode)
+            check_against_oracle(orc, src, w, mode, out, what=f"{shape} k={k}")
+
+
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
+@pytest.mark.parametrize("mode", MODES)
+def test_integer_weights_bit_exact(orc, dtype, mode):
+    g = np.random.default_rng(200 + MODES.index(mode))
+    for shape, k, D in [((9, 33, 65), 3, 27), ((20, 40, 130), 3, 1), ((7, 70, 3), 5, 125),
+                        ((9, 33, 65), 5, 7), ((5, 40, 67), 7, 64), ((3, 2, 1), 9, 3),
+                        ((12, 35, 70), 3, 1000), ((6, 20, 33), 11, 1 << 20),
+                        ((6, 20, 33), 1, 2), ((4, 9, 9), 15, (1 << 29))]:
+        src = _vol(g, shape, dtype)
+        w = g.integers(-8, 9, (k, k, k)).astype(np.int32)
+        out = run_filter(src, w, mode, divisor=D)
+        check_against_oracle(orc, src, w, mode, out, divisor=D, what=f"{shape} k={k} D={D}")
+
+
+def test_integer_weights_on_float_volume(orc):
+    g = np.random.default_rng(7)
+    src = _vol(g, (9, 33, 65), np.float32)
+    w = g.integers(-5, 6, (5, 5, 5)).astype(np.int32)
+    out = run_filter(src, w, "mirror", divisor=9)
+    check_against_oracle(orc, src, w, "mirror", out, divisor=9)
+
+
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16, np.float32])
+def test_delta_is_identity_bit_exact(dtype):
+    g = np.random.default_rng(3)
+    src = _vol(g, (11, 37, 71), dtype)
+    for k, mode in itertools.product((1, 3, 7, 15), MODES):
+        w = np.zeros((k, k, k), np.float32)
+        w[k // 2, k // 2, k // 2] = 1.0
+        assert np.array_equal(run_filter(src, w, mode), src), (k, mode)
+
+
+def test_off_centre_delta_orientation():
+    src = np.arange(5 * 6 * 7, dtype=np.float32).reshape(5, 6, 7)
+    w = np.zeros((3, 3, 3), np.float32)
+    w[1, 1, 2] = 1.0  # reads x + 1
+    out = run_filter(src, w, "clamp")
+    assert np.array_equal(out[:, :, :-1], src[:, :, 1:])
+    assert np.array_equal(out[:, :, -1], src[:, :, -1])
+    w = np.zeros((3, 3, 3), np.float32)
+    w[2, 1, 1] = 1.0  # reads z + 1
+    out = run_filter(src, w, "wrap")
+    assert np.array_equal(out, np.roll(src, -1, axis=0))
+
+
+def test_deterministic_and_all_cells_written(orc):
+    g = np.random.default_rng(5)
+    src = _vol(g, (33, 65, 129), np.float32)
+    w = g.standard_normal((7, 7, 7)).astype(np.float32)
+    a = run_filter(src, w, "clamp")
+    b = run_filter(src, w, "clamp")
+    assert not np.isnan(a).any()
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def test_argument_errors_leave_dst_untouched():
+    import torch
+    from paper_2203_10213_amd import vkt
+    src = to_device(np.zeros((4, 5, 6), np.float32))
+    dst = sentinel_like(src)
+    other = to_device(np.zeros((4, 5, 7), np.float32))
+    u8 = to_device(np.zeros((4, 5, 6), np.uint8))
+    hs, hd = vkt.volume_from_tensor(src), vkt.volume_from_tensor(dst)
+    ho, h8 = vkt.volume_from_tensor(other), vkt.volume_from_tensor(u8)
+    hf = vkt.vktFilterCreate(np.ones((3, 3, 3), np.float32))
+    try:
+        for d, s, m in [(hd, ho, 0), (hd, h8, 0), (hs, hs, 0), (hd, hs, 9), (hd, hs, -1)]:
+            with pytest.raises(vkt.VktError) as e:
+                vkt.vktApplyFilter(d, s, hf, m)
+            assert e.value.code == vkt.vktInvalidValue
+        # overlapping views of one buffer
+        big = torch.zeros(2 * 4 * 5 * 6, dtype=torch.float32, device="cuda")
+        a = vkt.vktStructuredVolumeCreateFromDevicePtr((6, 5, 4), vkt.vktDataFormatFloat32,
+                                                       big.data_ptr())
+        b = vkt.vktStructuredVolumeCreateFromDevicePtr((6, 5, 4), vkt.vktDataFormatFloat32,
+                                                       big.data_ptr() + 4 * 10)
+        with pytest.raises(vkt.VktError):
+            vkt.vktApplyFilter(a, b, hf, 0)
+        vkt.vktStructuredVolumeDestroy(a)
+        vkt.vktStructuredVolumeDestroy(b)
+        torch.cuda.synchronize()
+        assert torch.isnan(dst).all()
+        # a destroyed handle is rejected
+        vkt.vktStructuredVolumeDestroy(ho)
+        with pytest.raises(vkt.VktError):
+            vkt.vktApplyFilter(hd, ho, hf, 0)
+        # integer filter whose sum would overflow the exact integer path
+        hbig = vkt.vktFilterCreateInt(np.full((15, 15, 15), 8000, np.int32), 1)
+        u16a = to_device(np.zeros((4, 5, 6), np.uint16))
+        u16b = to_device(np.zeros((4, 5, 6), np.uint16))
+        ha, hb = vkt.volume_from_tensor(u16a), vkt.volume_from_tensor(u16b)
+        with pytest.raises(vkt.VktError) as e:
+            vkt.vktApplyFilter(hb, ha, hbig, 0)
+        assert e.value.code == vkt.vktUnsupported
+        for h in (ha, hb):
+            vkt.vktStructuredVolumeDestroy(h)
+        vkt.vktFilterDestroy(hbig)
+    finally:
+        vkt.vktFilterDestroy(hf)
+        for h in (hs, hd, h8):
+            vkt.vktStructuredVolumeDestroy(h)
+
+
+def test_owned_volumes_and_stream():
+    """Owned volumes start zero-filled; all work runs on the thread's stream."""
+    import torch
+    from paper_2203_10213_amd import vkt
+    s = torch.cuda.Stream()
+    vkt.vktSetStream(s)
+    dims = (40, 30, 20)
+    a = vkt.vktStructuredVolumeCreate(dims, vkt.vktDataFormatUInt16, lo=0, hi=65535)
+    b = vkt.vktStructuredVolumeCreate(dims, vkt.vktDataFormatUInt16, lo=0, hi=65535)
+    box = vkt.vktFilterCreate(np.full((3, 3, 3), 1.0 / 27, np.float32))
+    ident = vkt.vktFilterCreate(np.ones((1, 1, 1), np.float32))
+    out = torch.full((20, 30, 40), 7, dtype=torch.int16, device="cuda").view(torch.uint16)
+    torch.cuda.synchronize()
+    ho = vkt.volume_from_tensor(out)
+    try:
+        vkt.vktApplyFilter(ho, b, ident, "clamp")  # b is still all zero
+        vkt.vktSynchronize()
+        assert (out.cpu().numpy() == 0).all()
+        vkt.vktFill(a, 1000.0)
+        vkt.vktApplyFilter(b, a, box, "clamp")
+        vkt.vktApplyFilter(ho, b, ident, "clamp")
+        vkt.vktSynchronize()
+        assert (out.cpu().numpy() == 1000).all()
+    finally:
+        vkt.vktSetStream(None)
+        for f in (box, ident):
+            vkt.vktFilterDestroy(f)
+        for h in (a, b, ho):
+            vkt.vktStructuredVolumeDestroy(h)
+
+
+# ---------------------------------------------------- workload configurations --
+
+def test_c1_64cube_gaussian_full(orc):
+    """64^3 float32 U[0,1), 3^3 Gaussian sigma 1, clamp: every cell."""
+    from paper_2203_10213_amd import synth
+    src = synth.uniform_f32((64, 64, 64), synth.SEEDS["c1"])
+    w = synth.gaussian_weights(3, 1.0)
+    out = run_filter(src, w, "clamp")
+    err = check_against_oracle(orc, src, w, "clamp", out, what="C1")
+    assert err <= 1e-5
+
+
+def test_c2a_ct_phantom_box27_full(orc):
+    """512^3 uint8 CT-like phantom, integer 3^3 box / 27: bit-exact, every cell."""
+    from paper_2203_10213_amd import synth
+    src = synth.ct_phantom_u8(512, synth.SEEDS["c2a"])
+    w, D = synth.box_int(3)
+    out = run_filter(src, w, "clamp", divisor=D)
+    check_against_oracle(orc, src, w, "clamp", out, divisor=D, what="C2a")
+
+
+def test_c2b_smoothed_noise_gauss5_sampled(orc):
+    """512^3 float32 smoothed noise, 5^3 Gaussian sigma 1.5: 200k sampled
+    cells plus all corners/edges against the oracle."""
+    import torch
+    from paper_2203_10213_amd import synth
+    src_t = synth.smoothed_noise_f32(512, 4.0, synth.SEEDS["c2b"], device="cuda")
+    src = src_t.cpu().numpy()
+    w = synth.gaussian_weights(5, 1.5)
+    out = run_filter(src, w, "clamp", src_t=src_t)
+    pts = sample_points(src.shape, 200000, 77)
+    check_against_oracle(orc, src, w, "clamp", out, pts=pts, what="C2b")
+    del src_t
+    torch.cuda.empty_cache()
