@@ -151,7 +151,7 @@ vktError vktFillRangeSV(vktStructuredVolume volume, int32_t firstX,
  * always use exact integer arithmetic.
  * Errors: vktInvalidValue for bad handles, mismatched or overlapping volumes
  * or a mode out of range; vktUnsupported when an integer-weight filter's
- * sum |w| * max(format) would exceed 2^30 or a plane exceeds 2^31 cells. */
+ * sum |w| * max(format) would exceed 2^30 or one z-plane exceeds 2^31 bytes. */
 vktError vktApplyFilter(vktStructuredVolume dst, vktStructuredVolume src,
                         vktFilter filter, vktAddressMode mode);
 

@@ -326,7 +326,9 @@ vktError vktApplyFilter(vktStructuredVolume dst, vktStructuredVolume src, vktFil
     const char* d0 = static_cast<const char*>(dst->dev);
     const char* s0 = static_cast<const char*>(src->dev);
     if (d0 < s0 + bytes && s0 < d0 + bytes) return vktInvalidValue;  // overlap
-    if ((int64_t)src->dims[0] * src->dims[1] >= (int64_t(1) << 31)) return vktUnsupported;
+    // in-plane byte offsets are 32-bit in the kernels
+    if ((int64_t)src->dims[0] * src->dims[1] * vkt::cell_bytes(src->fmt) >= (int64_t(1) << 31))
+        return vktUnsupported;
 
     vkt::FilterJob j{};
     j.src = src->dev;
@@ -346,7 +348,9 @@ vktError vktApplyFilter(vktStructuredVolume dst, vktStructuredVolume src, vktFil
     if (filt->is_int && src->fmt != vktDataFormatFloat32) {
         const int64_t mx = src->fmt == vktDataFormatUInt8 ? 255 : 65535;
         if (filt->sum_abs_int * mx > (int64_t(1) << 30)) return vktUnsupported;
-        j.int_acc = true;
+        // FP32 sums of integer products are exact while |partial sums| < 2^24;
+        // beyond that the kernel accumulates in int32.
+        j.int_acc = filt->sum_abs_int * mx >= (int64_t(1) << 24);
         j.div2D = vkt::make_udiv(2u * (uint32_t)filt->divisor);
     }
     j.vec_store = (j.X % 4 == 0) &&

@@ -1,5 +1,6 @@
-// vkt_filter_valu.hip -- ApplyFilter on the vector ALUs (FP32 FMA, or exact
-// 24-bit integer multiply-add for integer-weight filters on integer cells).
+// vkt_filter_valu.hip -- ApplyFilter on the vector ALUs: FP32 fused
+// multiply-add, or exact 24-bit integer multiply-add for integer-weight
+// filters whose sums could leave the exactly representable FP32 range.
 //
 // Operation (paper Sec. 3.2 "Volume Manipulation"; benchmarked as a Gaussian
 // blur of structured volumes in Sec. 4.3): for every output cell,
@@ -8,17 +9,20 @@
 // Mapping to gfx950:
 //  * A workgroup of 256 threads owns a 64 x 32 (x, y) output tile and marches
 //    through a z-slab of output planes.  Each input plane of the slab, with an
-//    r-wide halo in x and y, is gathered once from HBM (the address mode is
-//    applied to halo coordinates only, through per-thread offsets computed
-//    once per workgroup) and staged in LDS, double buffered.
+//    r-wide halo in x and y, is gathered once (address mode applied to halo
+//    coordinates only, through per-thread 32-bit in-plane offsets computed once
+//    per workgroup) and staged in LDS as FP32 (or int32), double buffered; the
+//    next plane's loads are in flight while the current plane is computed.
 //  * Input-stationary z ring: a thread owns 4 (x) x 2 (y) output columns and
-//    keeps k partial sums per output, one per output plane zi - c + r that the
-//    current input plane zi contributes to.  Each input plane is read from LDS
-//    once per thread (16-byte reads of its (4+k-1)-wide row windows) and
-//    feeds all k^3 taps; after the plane, the finished output plane (the
-//    ring's oldest) is rounded and stored and the ring advances.
-//  * Workgroups are numbered XCD-aware so that tiles adjacent in x/y at the
-//    same z run on the same XCD and share its L2 for the halo re-reads.
+//    keeps k partial sums per output, one for each output plane zi - c + r the
+//    current input plane zi feeds.  A plane is read from LDS once per thread
+//    (16-byte reads of its (4+k-1)-wide row windows) and feeds all k^3 taps.
+//    After the plane, the ring's oldest entry is a finished output: it is
+//    rounded, stored, and the ring advances.
+//  * Weights are uniform: they are read with scalar loads as the operand of
+//    each multiply-add, re-issued per row group so they are never spilled.
+//  * Workgroups are numbered XCD-aware so tiles adjacent in x/y at the same z
+//    share an XCD's L2 for their halo re-reads.
 #include "vkt_internal.h"
 
 #include <type_traits>
@@ -33,13 +37,34 @@ constexpr int kTX = kBX * kVX, kTY = kBY * kVY;      // 64 x 32 tile
 template <int K>
 struct Geo {
     static constexpr int R = (K - 1) / 2;
-    static constexpr int HX = kTX + 2 * R;             // halo tile width
-    static constexpr int HY = kTY + 2 * R;             // halo tile height
-    static constexpr int P = (HX + 3) & ~3;            // LDS row pitch (cells)
-    static constexpr int NE = (HX * HY + kNT - 1) / kNT;  // halo cells / thread
-    static constexpr int WX = kVX + K - 1;             // row window per thread
-    static constexpr int NR = (WX + 3) / 4;            // 16-byte reads per row
+    static constexpr int HX = kTX + 2 * R;                // halo tile width
+    static constexpr int HY = kTY + 2 * R;                // halo tile height
+    static constexpr int P = (HX + 3) & ~3;               // LDS row pitch (cells)
+    static constexpr int NE = (HX * HY + kNT - 1) / kNT;  // halo cells per thread
+    static constexpr int WX = kVX + K - 1;                // row window per thread
+    static constexpr int NR = (WX + 3) / 4;               // 16-byte reads per row
+    static constexpr int NROW = kVY + K - 1;              // input rows per thread
     static_assert(4 * (kBX - 1) + 4 * NR <= P, "row window exceeds LDS pitch");
+};
+
+struct ValuArgs {
+    int32_t X, Y, Z;
+    int32_t mode;         // vktAddressMode
+    int32_t tz;           // output planes per slab
+    int32_t tiles_x, tiles_y;
+    uint32_t nblocks;
+    int32_t epi;          // kEpi* below
+    int32_t D;            // integer filter divisor
+    UDiv div2D;           // magic constants for 2D
+    float inv_D;
+    int32_t vec_ok;       // X % 4 == 0 and dst 4-cell aligned
+};
+
+enum : int32_t {
+    kEpiFloat = 0,        // float32 cells, float weights: store T
+    kEpiFloatDiv = 1,     // float32 cells, integer weights: store T / D
+    kEpiRound = 2,        // integer cells, float weights: floor(T + 1/2), saturate
+    kEpiIntDiv = 3        // integer cells, integer weights: floor((2T + D) / 2D)
 };
 
 // Address mode on one axis; -1 means "outside, reads zero" (border).
@@ -68,7 +93,31 @@ __device__ inline uint32_t xcd_remap(uint32_t b, uint32_t n)
     return xcd < rem ? xcd * (q + 1) + idx : rem * (q + 1) + (xcd - rem) * q + idx;
 }
 
-template <typename T> __device__ inline float to_f(T v) { return (float)v; }
+// An SGPR value the compiler cannot see through: adding it to a uniform index
+// keeps loads inside the loop iteration that uses them.
+__device__ inline int opaque_zero()
+{
+    int z = 0;
+    asm volatile("" : "+s"(z));
+    return z;
+}
+
+// Raw buffer loads: SGPR resource (base, size) + 32-bit VGPR byte offset.
+// An offset at or beyond the resource size reads 0 (used for border cells).
+constexpr uint32_t kRsrcWord3 = 0x00020000u;   // gfx9-family raw buffer
+constexpr uint32_t kOutside = 0x80000000u;     // byte offset that reads 0
+
+template <typename T>
+__device__ inline T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    if constexpr (sizeof(T) == 1) {
+        return (T)__builtin_amdgcn_raw_buffer_load_b8(r, (int)off, 0, 0);
+    } else if constexpr (sizeof(T) == 2) {
+        return (T)__builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0);
+    } else {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+    }
+}
 
 template <bool IACC> struct AccT { using type = float; };
 template <> struct AccT<true> { using type = int32_t; };
@@ -76,7 +125,7 @@ template <> struct AccT<true> { using type = int32_t; };
 __device__ inline float mac(float w, float v, float acc) { return fmaf(w, v, acc); }
 __device__ inline int32_t mac(int32_t w, int32_t v, int32_t acc)
 {
-    return __mul24(w, v) + acc;  // |w| < 2^23 and cells < 2^16: exact
+    return __mul24(w, v) + acc;  // |w| < 2^23, cells < 2^16: exact
 }
 
 __device__ inline uint32_t udiv(uint32_t n, UDiv d)
@@ -86,30 +135,29 @@ __device__ inline uint32_t udiv(uint32_t n, UDiv d)
 }
 
 // Stored value of one finished output.
-template <typename T, bool IACC>
-__device__ inline T finish(typename AccT<IACC>::type acc, const FilterJob& j)
+template <typename T, typename Acc>
+__device__ inline T finish(Acc acc, const ValuArgs& a)
 {
     if constexpr (std::is_same<T, float>::value) {
-        return j.int_filter ? acc * j.inv_D : acc;
+        return a.epi == kEpiFloatDiv ? (float)acc * a.inv_D : (float)acc;
     } else {
-        constexpr float kMax = std::is_same<T, uint8_t>::value ? 255.f : 65535.f;
-        if constexpr (IACC) {
-            // floor((2T + D) / (2D)), exact; T < 0 always stores 0
-            if (acc < 0) return (T)0;
-            const uint32_t q = udiv(2u * (uint32_t)acc + (uint32_t)j.D, j.div2D);
+        constexpr int kMax = std::is_same<T, uint8_t>::value ? 255 : 65535;
+        if (a.epi == kEpiIntDiv) {
+            // acc is an exact integer (int32, or float below 2^24)
+            const int32_t t = (int32_t)acc;
+            if (t < 0) return (T)0;
+            const uint32_t q = udiv(2u * (uint32_t)t + (uint32_t)a.D, a.div2D);
             return (T)(q > (uint32_t)kMax ? (uint32_t)kMax : q);
-        } else {
-            const float q = floorf(acc + 0.5f);
-            return (T)fminf(fmaxf(q, 0.f), kMax);
         }
+        const float q = floorf((float)acc + 0.5f);
+        return (T)fminf(fmaxf(q, 0.f), (float)kMax);
     }
 }
 
-template <typename T, int K, bool IACC>
+template <typename T, int K, bool IACC, bool BORDER>
 __global__ __launch_bounds__(kNT) void filter_valu_kernel(
     const T* __restrict__ src, T* __restrict__ dst,
-    const typename AccT<IACC>::type* __restrict__ w, FilterJob j, int32_t tz,
-    int32_t tiles_x, int32_t tiles_y, uint32_t nblocks)
+    const typename AccT<IACC>::type* __restrict__ w, ValuArgs a)
 {
     using G = Geo<K>;
     using Acc = typename AccT<IACC>::type;
@@ -117,49 +165,43 @@ __global__ __launch_bounds__(kNT) void filter_valu_kernel(
     __shared__ __align__(16) Acc lds[2][G::HY * G::P];
 
     const int t = threadIdx.x, tx = t % kBX, ty = t / kBX;
-    const uint32_t lid = xcd_remap(blockIdx.x, nblocks);
-    const uint32_t ntiles = (uint32_t)tiles_x * (uint32_t)tiles_y;
+    const uint32_t lid = xcd_remap(blockIdx.x, a.nblocks);
+    const uint32_t ntiles = (uint32_t)a.tiles_x * (uint32_t)a.tiles_y;
     const int tile = (int)(lid % ntiles), slab = (int)(lid / ntiles);
-    const int x0 = (tile % tiles_x) * kTX, y0 = (tile / tiles_x) * kTY;
-    const int zb = slab * tz, ze = min(zb + tz, j.Z);
-    const int64_t plane = (int64_t)j.X * j.Y;
+    const int x0 = (tile % a.tiles_x) * kTX, y0 = (tile / a.tiles_x) * kTY;
+    const int zb = slab * a.tz, ze = min(zb + a.tz, a.Z);
+    const int64_t plane = (int64_t)a.X * a.Y;
 
-    // Halo gather offsets: same (x, y) cells for every plane of the slab.
-    int32_t goff[G::NE];  // in-plane source offset, -1 = zero cell
-    int32_t loff[G::NE];  // LDS slot, -1 = none
+    // Halo gather: the same (x, y) cells for every plane of the slab.
+    uint32_t goff[G::NE];   // in-plane source byte offset (kOutside: zero cell)
+    int32_t loff[G::NE];    // LDS slot
 #pragma unroll
     for (int i = 0; i < G::NE; ++i) {
-        const int e = t + i * kNT;
-        if (e < G::HX * G::HY) {
-            const int hy = e / G::HX, hx = e - hy * G::HX;
-            const int gx = addr_map((int64_t)x0 - R + hx, j.X, j.mode);
-            const int gy = addr_map((int64_t)y0 - R + hy, j.Y, j.mode);
-            goff[i] = (gx < 0 || gy < 0) ? -1 : gy * j.X + gx;
-            loff[i] = hy * G::P + hx;
-        } else {
-            goff[i] = -1;
-            loff[i] = -1;
-        }
+        int e = t + i * kNT;
+        if (e >= G::HX * G::HY) e = G::HX * G::HY - 1;  // duplicate write of the last cell
+        const int hy = e / G::HX, hx = e - hy * G::HX;
+        const int gx = addr_map((int64_t)x0 - R + hx, a.X, a.mode);
+        const int gy = addr_map((int64_t)y0 - R + hy, a.Y, a.mode);
+        goff[i] = (gx < 0 || gy < 0)
+                      ? kOutside
+                      : ((uint32_t)gy * (uint32_t)a.X + (uint32_t)gx) * (uint32_t)sizeof(T);
+        loff[i] = hy * G::P + hx;
     }
 
+    const int32_t plane_bytes = (int32_t)(plane * (int64_t)sizeof(T));  // < 2^31 (host check)
     Acc stage[G::NE];
     auto gather = [&](int zi) {
-        const int gz = addr_map(zi, j.Z, j.mode);
-        const T* base = src + (gz < 0 ? 0 : (int64_t)gz * plane);
+        const int gz = addr_map(zi, a.Z, a.mode);  // -1 only for border: a zero plane
+        const char* base = reinterpret_cast<const char*>(src) +
+                           (gz < 0 ? 0 : (int64_t)gz * plane_bytes);
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<char*>(base), (short)0, gz < 0 ? 0 : plane_bytes, (int)kRsrcWord3);
 #pragma unroll
-        for (int i = 0; i < G::NE; ++i) {
-            Acc v = 0;
-            if (gz >= 0 && goff[i] >= 0) {
-                if constexpr (IACC) v = (int32_t)base[goff[i]];
-                else v = to_f(base[goff[i]]);
-            }
-            stage[i] = v;
-        }
+        for (int i = 0; i < G::NE; ++i) stage[i] = (Acc)buf_load<T>(rs, goff[i]);
     };
     auto put = [&](Acc* buf) {
 #pragma unroll
-        for (int i = 0; i < G::NE; ++i)
-            if (loff[i] >= 0) buf[loff[i]] = stage[i];
+        for (int i = 0; i < G::NE; ++i) buf[loff[i]] = stage[i];
     };
 
     Acc acc[K][kVY][kVX];
@@ -176,57 +218,94 @@ __global__ __launch_bounds__(kNT) void filter_valu_kernel(
     __syncthreads();
 
     const int ox = x0 + kVX * tx, oy = y0 + kVY * ty;
+    const bool vec = a.vec_ok && ox + kVX <= a.X;
     for (int zi = zi_beg; zi < zi_end; ++zi) {
         const int cur = (zi - zi_beg) & 1;
-        const bool more = zi + 1 < zi_end;
-        if (more) gather(zi + 1);
+        // next plane's loads in flight during this plane's taps (the last
+        // iteration re-reads a valid plane and discards it)
+        gather(min(zi + 1, zi_end - 1));
 
-        // ---- all k^3 taps of input plane zi, for the k output planes it feeds
-        const Acc* buf = lds[cur];
-        constexpr int NROW = kVY + K - 1;
-constexpr int kRowUnroll = K <= 5 ? NROW : 1;
-#pragma unroll kRowUnroll
-        for (int jr = 0; jr < NROW; ++jr) {
-            Acc v[G::NR * 4];
-            const Acc* row = buf + (kVY * ty + jr) * G::P + kVX * tx;
+        const Acc* buf = lds[cur] + (kVY * ty) * G::P + kVX * tx;
+        using V4 = typename std::conditional<IACC, int4, float4>::type;
+        if constexpr (K <= 5) {
+            // all (2 + k - 1) row windows in registers, then taps grouped by
+            // filter plane c (k = 3) or filter row (c, b) (k = 5), so that at
+            // most 9 scalar weights are live per group
+            Acc v[G::NROW][G::NR * 4];
 #pragma unroll
-            for (int q = 0; q < G::NR; ++q) {
-                const auto u = *reinterpret_cast<const typename std::conditional<
-                    IACC, int4, float4>::type*>(row + 4 * q);
-                v[4 * q + 0] = u.x; v[4 * q + 1] = u.y;
-                v[4 * q + 2] = u.z; v[4 * q + 3] = u.w;
-            }
+            for (int jr = 0; jr < G::NROW; ++jr)
 #pragma unroll
-            for (int vy = 0; vy < kVY; ++vy) {
-                const int b = jr - vy;
-                if (b < 0 || b >= K) continue;
+                for (int q = 0; q < G::NR; ++q) {
+                    const V4 u = *reinterpret_cast<const V4*>(buf + jr * G::P + 4 * q);
+                    v[jr][4 * q + 0] = u.x;
+                    v[jr][4 * q + 1] = u.y;
+                    v[jr][4 * q + 2] = u.z;
+                    v[jr][4 * q + 3] = u.w;
+                }
 #pragma unroll
-                for (int c = 0; c < K; ++c)
+            for (int c = 0; c < K; ++c) {
+                const int oc = K <= 3 ? opaque_zero() : 0;
 #pragma unroll
-                    for (int a = 0; a < K; ++a) {
-                        const Acc wv = w[(c * K + b) * K + a];
+                for (int b = 0; b < K; ++b) {
+                    const Acc* wp = w + (K <= 3 ? oc : opaque_zero()) + (c * K + b) * K;
 #pragma unroll
-                        for (int vx = 0; vx < kVX; ++vx)
-                            acc[c][vy][vx] = mac(wv, v[vx + a], acc[c][vy][vx]);
+                    for (int aa = 0; aa < K; ++aa) {
+                        const Acc wv = wp[aa];
+#pragma unroll
+                        for (int vy = 0; vy < kVY; ++vy)
+#pragma unroll
+                            for (int vx = 0; vx < kVX; ++vx)
+                                acc[c][vy][vx] = mac(wv, v[b + vy][vx + aa], acc[c][vy][vx]);
                     }
+                }
+            }
+        } else {
+            // stream the row windows; k scalar weights live per (row, vy, c)
+#pragma unroll 1
+            for (int jr = 0; jr < G::NROW; ++jr) {
+                Acc v[G::NR * 4];
+#pragma unroll
+                for (int q = 0; q < G::NR; ++q) {
+                    const V4 u = *reinterpret_cast<const V4*>(buf + jr * G::P + 4 * q);
+                    v[4 * q + 0] = u.x;
+                    v[4 * q + 1] = u.y;
+                    v[4 * q + 2] = u.z;
+                    v[4 * q + 3] = u.w;
+                }
+#pragma unroll
+                for (int vy = 0; vy < kVY; ++vy) {
+                    const int b = jr - vy;
+                    if (b < 0 || b >= K) continue;
+#pragma unroll
+                    for (int c = 0; c < K; ++c) {
+                        const Acc* wp = w + opaque_zero() + (c * K + b) * K;
+#pragma unroll
+                        for (int aa = 0; aa < K; ++aa) {
+                            const Acc wv = wp[aa];
+#pragma unroll
+                            for (int vx = 0; vx < kVX; ++vx)
+                                acc[c][vy][vx] = mac(wv, v[vx + aa], acc[c][vy][vx]);
+                        }
+                    }
+                }
             }
         }
 
-        if (more) put(lds[cur ^ 1]);
+        put(lds[cur ^ 1]);
 
-        // ---- the ring's oldest plane zo = zi - r is complete
+        // ---- the ring's oldest entry is output plane zo = zi - r
         const int zo = zi - R;
         if (zo >= zb) {
             T* orow = dst + (int64_t)zo * plane;
 #pragma unroll
             for (int vy = 0; vy < kVY; ++vy) {
                 const int y = oy + vy;
-                if (y >= j.Y) continue;
-                T* o = orow + (int64_t)y * j.X + ox;
+                if (y >= a.Y) continue;
+                T* o = orow + (int64_t)y * a.X + ox;
                 T r4[kVX];
 #pragma unroll
-                for (int vx = 0; vx < kVX; ++vx) r4[vx] = finish<T, IACC>(acc[K - 1][vy][vx], j);
-                if (j.vec_store && ox + kVX <= j.X) {
+                for (int vx = 0; vx < kVX; ++vx) r4[vx] = finish<T>(acc[K - 1][vy][vx], a);
+                if (vec) {
                     if constexpr (sizeof(T) == 1) {
                         *reinterpret_cast<uchar4*>(o) = make_uchar4(r4[0], r4[1], r4[2], r4[3]);
                     } else if constexpr (sizeof(T) == 2) {
@@ -237,7 +316,7 @@ constexpr int kRowUnroll = K <= 5 ? NROW : 1;
                 } else {
 #pragma unroll
                     for (int vx = 0; vx < kVX; ++vx)
-                        if (ox + vx < j.X) o[vx] = r4[vx];
+                        if (ox + vx < a.X) o[vx] = r4[vx];
                 }
             }
         }
@@ -259,25 +338,43 @@ constexpr int kRowUnroll = K <= 5 ? NROW : 1;
 template <typename T, int K, bool IACC>
 hipError_t launch_k(const FilterJob& j, hipStream_t s)
 {
-    const int tiles_x = (j.X + kTX - 1) / kTX, tiles_y = (j.Y + kTY - 1) / kTY;
-    const int64_t ntiles = (int64_t)tiles_x * tiles_y;
+    ValuArgs a{};
+    a.X = j.X;
+    a.Y = j.Y;
+    a.Z = j.Z;
+    a.mode = j.mode;
+    a.tiles_x = (j.X + kTX - 1) / kTX;
+    a.tiles_y = (j.Y + kTY - 1) / kTY;
+    const int64_t ntiles = (int64_t)a.tiles_x * a.tiles_y;
     // z-slab depth: enough workgroups to fill 256 CUs several times over,
     // slabs deep enough to amortise the 2r halo planes.
-    int64_t want_slabs = (2048 + ntiles - 1) / ntiles;
+    const int64_t want_slabs = (2048 + ntiles - 1) / ntiles;
     int tz = (int)((j.Z + want_slabs - 1) / want_slabs);
     const int tz_min = 4 > 2 * K ? 4 : 2 * K;
     if (tz < tz_min) tz = tz_min;
     if (tz > 64) tz = 64;
     if (tz > j.Z) tz = j.Z;
-    const int64_t slabs = (j.Z + tz - 1) / tz;
-    const int64_t nb = ntiles * slabs;
+    a.tz = tz;
+    const int64_t nb = ntiles * ((j.Z + tz - 1) / tz);
     if (nb > 0x7fffffff) return hipErrorInvalidValue;
+    a.nblocks = (uint32_t)nb;
+    if (j.fmt == vktDataFormatFloat32) a.epi = j.int_filter ? kEpiFloatDiv : kEpiFloat;
+    else a.epi = j.int_filter ? kEpiIntDiv : kEpiRound;
+    a.D = j.D;
+    a.div2D = j.div2D;
+    a.inv_D = j.inv_D;
+    a.vec_ok = j.vec_store ? 1 : 0;
     using Acc = typename AccT<IACC>::type;
     const Acc* w;
     if constexpr (IACC) w = j.wi; else w = j.wf;
-    hipLaunchKernelGGL((filter_valu_kernel<T, K, IACC>), dim3((unsigned)nb), dim3(kNT),
-                       0, s, static_cast<const T*>(j.src), static_cast<T*>(j.dst), w,
-                       j, tz, tiles_x, tiles_y, (uint32_t)nb);
+    const T* src = static_cast<const T*>(j.src);
+    T* dst = static_cast<T*>(j.dst);
+    if (j.mode == vktAddressModeBorder)
+        hipLaunchKernelGGL((filter_valu_kernel<T, K, IACC, true>), dim3((unsigned)nb),
+                           dim3(kNT), 0, s, src, dst, w, a);
+    else
+        hipLaunchKernelGGL((filter_valu_kernel<T, K, IACC, false>), dim3((unsigned)nb),
+                           dim3(kNT), 0, s, src, dst, w, a);
     return hipGetLastError();
 }
 
