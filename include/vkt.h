@@ -51,11 +51,18 @@ typedef enum vktAddressMode {
     vktAddressModeBorder = 3   /* zero outside */
 } vktAddressMode;
 
-/* Arithmetic used by vktApplyFilter on the calling thread. */
+/* Arithmetic used by vktApplyFilter on the calling thread, for filters with
+ * float weights and k >= 5 (integer-weight filters and k < 5 always run the
+ * exact vector-ALU path).  The split modes run the filter as an implicit GEMM
+ * on the matrix cores with 16-bit operand pieces and FP32 accumulation:
+ * UInt8/UInt16 cells are split exactly into fp16 pieces and the weights into
+ * two fp16 pieces (2 or 4 products); Float32 cells and weights are split
+ * into bf16 pieces, keeping 3 products (SplitBF16) or 6 (SplitBF16x6). */
 typedef enum vktPrecision {
-    vktPrecisionAuto = 0,      /* library chooses per call */
-    vktPrecisionFP32 = 1,      /* FP32 multiply-add on the vector ALUs */
-    vktPrecisionSplitBF16 = 2  /* bf16 matrix cores, split operands, FP32 sums */
+    vktPrecisionAuto = 0,        /* split (3 products) for k >= 5 */
+    vktPrecisionFP32 = 1,        /* FP32 multiply-add on the vector ALUs */
+    vktPrecisionSplitBF16 = 2,   /* matrix cores, 3 bf16 products for Float32 */
+    vktPrecisionSplitBF16x6 = 3  /* matrix cores, 6 bf16 products for Float32 */
 } vktPrecision;
 
 typedef struct vktStructuredVolume_* vktStructuredVolume;
@@ -145,10 +152,8 @@ vktError vktFillRangeSV(vktStructuredVolume volume, int32_t firstX,
  * rounded half-up (floor(q + 1/2)) and saturated; integer-weight filters on
  * integer formats compute floor((2T + D) / (2D)) exactly.
  * dst and src must have equal dims and format and must not overlap.
- * The arithmetic follows the thread's vktPrecision: FP32 runs on the vector
- * ALUs; SplitBF16 (and Auto for k >= 5 on float weights) runs on bf16 matrix
- * cores with split operands and FP32 accumulation.  Integer-weight filters
- * always use exact integer arithmetic.
+ * The arithmetic follows the thread's vktPrecision (see vktPrecision).
+ * Integer-weight filters always use exact integer arithmetic.
  * Errors: vktInvalidValue for bad handles, mismatched or overlapping volumes
  * or a mode out of range; vktUnsupported when an integer-weight filter's
  * sum |w| * max(format) would exceed 2^30 or one z-plane exceeds 2^31 bytes. */

@@ -28,6 +28,7 @@ struct vktFilter_ {
     bool is_int;
     int32_t divisor;
     int64_t sum_abs_int;        // sum |w| for integer filters
+    float wscale;               // power of two: max|w| * wscale in [2^14, 2^15)
     float* d_wf;                // device float weights (k^3)
     int32_t* d_wi;              // device int weights (k^3), integer filters
     int device;
@@ -49,6 +50,7 @@ ThreadState& state()
         if (const char* p = std::getenv("VKT_PRECISION")) {
             if (!std::strcmp(p, "fp32")) t_state.precision = vktPrecisionFP32;
             else if (!std::strcmp(p, "splitbf16")) t_state.precision = vktPrecisionSplitBF16;
+            else if (!std::strcmp(p, "splitbf16x6")) t_state.precision = vktPrecisionSplitBF16x6;
         }
     }
     return t_state;
@@ -168,8 +170,17 @@ vktError create_filter(vktFilter* out, int32_t k, const float* wf, const int32_t
         if (dwi) (void)hipFree(dwi);
         return from_hip(e);
     }
+    // power-of-two weight scale for fp16 operand splitting
+    float amax = 0.f;
+    for (int i = 0; i < n; ++i) amax = std::fmax(amax, std::fabs(hf[i]));
+    float wscale = 1.f;
+    if (amax > 0.f && std::isfinite(amax)) {
+        int ex = 0;
+        std::frexp(amax, &ex);                 // amax in [2^(ex-1), 2^ex)
+        wscale = std::ldexp(1.f, 15 - ex);     // amax * wscale in [2^14, 2^15)
+    }
     auto* f = new (std::nothrow) vktFilter_{k, wi != nullptr, wi ? divisor : 1, sum_abs,
-                                            dwf, dwi, device};
+                                            wscale, dwf, dwi, device};
     if (!f) {
         (void)hipFree(dwf);
         if (dwi) (void)hipFree(dwi);
@@ -355,6 +366,15 @@ vktError vktApplyFilter(vktStructuredVolume dst, vktStructuredVolume src, vktFil
     }
     j.vec_store = (j.X % 4 == 0) &&
                   (reinterpret_cast<uintptr_t>(dst->dev) % (4 * vkt::cell_bytes(src->fmt)) == 0);
+    j.wscale = filt->wscale;
+    // Plan: float-weight filters with k >= 5 run on the matrix cores unless
+    // the thread asks for FP32; everything else (k < 5, integer weights,
+    // whose results are exact integers) runs on the vector ALUs.
+    const vktPrecision prec = state().precision;
+    const bool mfma = !filt->is_int && filt->k >= 5 && prec != vktPrecisionFP32;
+    if (mfma)
+        return from_hip(vkt::launch_filter_mfma(j, prec == vktPrecisionSplitBF16x6,
+                                                state().stream));
     return from_hip(vkt::launch_filter_valu(j, state().stream));
 }
 
@@ -373,7 +393,7 @@ vktError vktGetStream(void** stream)
 
 vktError vktSetPrecision(vktPrecision p)
 {
-    if (p < vktPrecisionAuto || p > vktPrecisionSplitBF16) return vktInvalidValue;
+    if (p < vktPrecisionAuto || p > vktPrecisionSplitBF16x6) return vktInvalidValue;
     state().precision = p;
     return vktNoError;
 }

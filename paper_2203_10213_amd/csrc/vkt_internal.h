@@ -44,6 +44,7 @@ struct FilterJob {
     UDiv div2D;              // for 2*D
     float inv_D;             // 1/D for float outputs of integer filters
     bool vec_store;          // dst rows can take 16-B-aligned vector stores
+    float wscale;            // 2^s with max|w| * 2^s in [2^14, 2^15) (fp16 splitting)
 };
 
 // Kernel launchers (return the launch status).
@@ -53,5 +54,8 @@ hipError_t launch_fill_range(void* dst, int cell_bytes, int32_t X, int32_t Y,
                              const int32_t first[3], const int32_t last[3],
                              uint32_t raw_bits, hipStream_t s);
 hipError_t launch_filter_valu(const FilterJob& j, hipStream_t s);
+// Matrix-core path for float-weight filters with k >= 5.  six_products
+// selects the 6-product bf16 split for float32 volumes (else 3 products).
+hipError_t launch_filter_mfma(const FilterJob& j, bool six_products, hipStream_t s);
 
 }  // namespace vkt

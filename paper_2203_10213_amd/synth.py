@@ -223,4 +223,5 @@ def ellipsoid_phantom_u16(shape=(1024, 2048, 2048), n_ell=5000,
         sl = sl + nz * torch.sqrt(sl)
         out[z0:z1] = torch.clamp(torch.floor(sl + 0.5), 0, 65535).to(torch.int32)
     del v
-    return out.to(torch.uint16) if hasattr(torch, "uint16") else out
+    # int32 in [0, 65535] -> the same 16 bits, viewed as uint16
+    return out.to(torch.int16).view(torch.uint16)

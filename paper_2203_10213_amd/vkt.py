@@ -19,12 +19,12 @@ LIB_PATH = os.path.join(_HERE, "libvkt.so")
 vktNoError, vktInvalidValue, vktOutOfMemory, vktDeviceError, vktUnsupported = range(5)
 vktDataFormatUInt8, vktDataFormatUInt16, vktDataFormatFloat32 = range(3)
 vktAddressModeClamp, vktAddressModeWrap, vktAddressModeMirror, vktAddressModeBorder = range(4)
-vktPrecisionAuto, vktPrecisionFP32, vktPrecisionSplitBF16 = range(3)
+vktPrecisionAuto, vktPrecisionFP32, vktPrecisionSplitBF16, vktPrecisionSplitBF16x6 = range(4)
 
 MODES = {"clamp": vktAddressModeClamp, "wrap": vktAddressModeWrap,
          "mirror": vktAddressModeMirror, "border": vktAddressModeBorder}
 PRECISIONS = {"auto": vktPrecisionAuto, "fp32": vktPrecisionFP32,
-              "splitbf16": vktPrecisionSplitBF16}
+              "splitbf16": vktPrecisionSplitBF16, "splitbf16x6": vktPrecisionSplitBF16x6}
 TORCH_FORMAT = {torch.uint8: vktDataFormatUInt8, torch.uint16: vktDataFormatUInt16,
                 torch.float32: vktDataFormatFloat32}
 
