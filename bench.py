@@ -34,7 +34,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2",
                     choices=["c1", "c2", "c2a", "c2b", "c3a", "c3b", "c5"])
-    ap.add_argument("--precision", default="auto", choices=["auto", "fp32", "splitbf16"])
+    ap.add_argument("--precision", default=None,
+                    choices=["auto", "fp32", "splitbf16", "splitbf16x6"],
+                    help="default: fp32 for c1/c2 (the plain-path configurations), "
+                         "auto (split bf16/fp16 matrix path for k >= 5) otherwise")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample")
@@ -104,6 +107,45 @@ def stored_traffic(case_name):
     except (ValueError, KeyError):
         pass
     return None
+
+
+def arith_dtype(c, precision):
+    """The type the path computes in."""
+    if c["path"] == "mfma":
+        if c["src"].dtype.is_floating_point:
+            return "bf16x6->f32" if precision == "splitbf16x6" else "bf16x3->f32"
+        return "f16x2->f32"
+    if c["D"] is not None:
+        return "f32(exact int)"
+    return "f32"
+
+
+def kernel_path(c, precision):
+    """The library's plan rule: float-weight filters with k >= 5 run on the
+    matrix cores unless the precision is fp32; the rest on the vector ALUs."""
+    return "mfma" if (c["D"] is None and c["k"] >= 5 and precision != "fp32") else "valu"
+
+
+def case_roofline(c, ms):
+    """Algorithmic bytes (1 cell read + 1 cell written per output) and flops
+    (2 k^3 per output) over the measured time, against the roofline that
+    bounds this path: HBM, the FP32 vector ALUs, or the dense 16-bit matrix
+    cores (split products and Toeplitz zeros are overhead, not counted)."""
+    t = ms * 1e-3
+    bytes_alg = 2 * c["voxels"] * c["cell_bytes"]
+    flops = c["voxels"] * c["flops_per_voxel"]
+    gbs = bytes_alg / t / 1e9
+    tfs = flops / t / 1e12
+    peak_c = BF16_MFMA_PEAK_TF if c["path"] == "mfma" else FP32_VECTOR_PEAK_TF
+    if bytes_alg / (HBM_PEAK_GBS * 1e9) >= flops / (peak_c * 1e12):
+        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs / HBM_PEAK_GBS}
+    else:
+        roof = {"bound": "mfma" if c["path"] == "mfma" else "alu", "achieved": tfs,
+                "peak": peak_c, "unit": "TFLOP/s", "frac": tfs / peak_c}
+    return dict(case=c["name"], path=c["path"], ms=ms,
+                gvoxels_s=c["voxels"] / t / 1e9, hbm_gbs=gbs, hbm_frac=gbs / HBM_PEAK_GBS,
+                tflops=tfs, algorithmic_bytes=bytes_alg, flops=flops, roofline=roof)
 
 
 # ------------------------------------------------------------ CPU baseline --
@@ -180,10 +222,13 @@ def main():
     torch.cuda.set_device(dev)
     print(f"[bench] building inputs for {args.workload}", file=sys.stderr, flush=True)
     cases = make_cases(args.workload, dev)
+    if args.precision is None:
+        args.precision = "fp32" if args.workload in ("c1", "c2", "c2a", "c2b") else "auto"
     stream = torch.cuda.current_stream()
     vkt.vktSetStream(stream)
     vkt.vktSetPrecision(args.precision)
     for c in cases:
+        c["path"] = kernel_path(c, args.precision)
         c["dst"] = torch.empty_like(c["src"])
         c["hs"] = vkt.volume_from_tensor(c["src"])
         c["hd"] = vkt.volume_from_tensor(c["dst"])
@@ -225,25 +270,10 @@ def main():
     per_case = []
     for i, c in enumerate(cases):
         ms = sum(evs[s][i][0].elapsed_time(evs[s][i][1]) for s in range(K)) / K
-        bytes_alg = 2 * c["voxels"] * c["cell_bytes"]
-        flops = c["voxels"] * c["flops_per_voxel"]
-        gbs = bytes_alg / (ms * 1e-3) / 1e9
-        tfs = flops / (ms * 1e-3) / 1e12
-        per_case.append(dict(case=c["name"], ms=ms, gvoxels_s=c["voxels"] / (ms * 1e-3) / 1e9,
-                             hbm_gbs=gbs, hbm_frac=gbs / HBM_PEAK_GBS,
-                             fp32_tflops=tfs, fp32_frac=tfs / FP32_VECTOR_PEAK_TF,
-                             algorithmic_bytes=bytes_alg, flops=flops))
+        per_case.append(case_roofline(c, ms))
     dom = max(range(len(cases)), key=lambda i: per_case[i]["ms"])
     d = per_case[dom]
-    # bound: whichever roofline the algorithmic work hits first
-    t_hbm = d["algorithmic_bytes"] / (HBM_PEAK_GBS * 1e9)
-    t_alu = d["flops"] / (FP32_VECTOR_PEAK_TF * 1e12)
-    if t_hbm >= t_alu:
-        roof = {"bound": "hbm", "achieved": d["hbm_gbs"], "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": d["hbm_frac"]}
-    else:
-        roof = {"bound": "alu", "achieved": d["fp32_tflops"], "peak": FP32_VECTOR_PEAK_TF,
-                "unit": "TFLOP/s", "frac": d["fp32_frac"]}
+    roof = dict(d["roofline"])
     roof["kernel_case"] = d["case"]
     roof["traffic"] = stored_traffic(d["case"])
 
@@ -258,7 +288,7 @@ def main():
         "value": value, "unit": "Gvoxels/s", "n_gpus": 1, "steps": K,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "+".join(sorted({"f32" if c["D"] is None else "int32" for c in cases})),
+        "dtype": "+".join(sorted({arith_dtype(c, args.precision) for c in cases})),
         "data": "synthetic",
         "config": {"workload": args.workload,
                    "cases": [f"{c['name']} ({dtype[c['src'].dtype]} "
