@@ -113,7 +113,7 @@ def arith_dtype(c, precision):
     """The type the path computes in."""
     if c["path"] == "mfma":
         if c["src"].dtype.is_floating_point:
-            return "bf16x6->f32" if precision == "splitbf16x6" else "bf16x3->f32"
+            return "bf16x3->f32" if precision == "splitbf16" else "bf16x6->f32"
         return "f16x2->f32"
     if c["D"] is not None:
         return "f32(exact int)"

@@ -57,9 +57,11 @@ typedef enum vktAddressMode {
  * on the matrix cores with 16-bit operand pieces and FP32 accumulation:
  * UInt8/UInt16 cells are split exactly into fp16 pieces and the weights into
  * two fp16 pieces (2 or 4 products); Float32 cells and weights are split
- * into bf16 pieces, keeping 3 products (SplitBF16) or 6 (SplitBF16x6). */
+ * into bf16 pieces, keeping 3 products (SplitBF16: dropped terms up to
+ * 3 * 2^-16 of |w||s| per tap, faster) or 6 (SplitBF16x6 and Auto: dropped
+ * terms below 2^-22 of |w||s|). */
 typedef enum vktPrecision {
-    vktPrecisionAuto = 0,        /* split (3 products) for k >= 5 */
+    vktPrecisionAuto = 0,        /* split for k >= 5; 6 products for Float32 */
     vktPrecisionFP32 = 1,        /* FP32 multiply-add on the vector ALUs */
     vktPrecisionSplitBF16 = 2,   /* matrix cores, 3 bf16 products for Float32 */
     vktPrecisionSplitBF16x6 = 3  /* matrix cores, 6 bf16 products for Float32 */
@@ -160,6 +162,27 @@ vktError vktFillRangeSV(vktStructuredVolume volume, int32_t firstX,
 vktError vktApplyFilter(vktStructuredVolume dst, vktStructuredVolume src,
                         vktFilter filter, vktAddressMode mode);
 
+/* Batched form: dst[i] = ApplyFilter(src[i], filters[i]) for i < n, each
+ * pair exactly as vktApplyFilter would compute it, for volumes of different
+ * sizes and filters of different k.  The pairs are grouped into arithmetic
+ * classes (format, k, path); each class runs as one persistent launch whose
+ * workgroups take tile-slabs of all its volumes from a work queue, longest
+ * first; the class launches are the parallel nodes of one hipGraph that is
+ * launched on the calling thread's stream.  The plan (descriptors, work lists,
+ * weight pools, graph) is cached per batch signature -- volume pointers and
+ * dims, filter identities, mode, precision and stream -- so a repeated batch
+ * is one graph launch.  Outputs must not overlap any volume of the batch.
+ * Two calls with the same signature must not run concurrently (they share
+ * the plan's work queue).  With vktSetAutotune(1) the first plan of a batch
+ * size class times candidate z-slab depths per class on the real data (this
+ * writes the outputs and waits for the stream) and records the fastest;
+ * VKT_TUNE_CACHE=<file> keeps that table across processes.
+ * Errors: as vktApplyFilter for any pair; vktInvalidValue for n < 0, NULL
+ * arrays or overlapping outputs; vktOutOfMemory for the plan buffer. */
+vktError vktApplyFilterBatched(int32_t n, const vktStructuredVolume* dst,
+                               const vktStructuredVolume* src,
+                               const vktFilter* filters, vktAddressMode mode);
+
 /* ---- per-thread execution state (paper Sec. 3.1 ExecutionPolicy) -------- */
 
 /* stream is a hipStream_t (NULL = the default stream). */
@@ -167,6 +190,9 @@ vktError vktSetStream(void* stream);
 vktError vktGetStream(void** stream);
 vktError vktSetPrecision(vktPrecision precision);
 vktError vktGetPrecision(vktPrecision* precision);
+/* Enable (1) or disable (0) batched-plan autotuning on this thread (default:
+ * the VKT_AUTOTUNE environment variable, "1" enables). */
+vktError vktSetAutotune(int enable);
 
 /* Wait for the calling thread's stream; reports faults of enqueued work. */
 vktError vktSynchronize(void);

@@ -21,14 +21,32 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-I", os.path.join(PKG, "..", "include")]
 
 
+# Translation units compiled more than once, with their per-object flags.
+# The matrix-core kernels are built per tile shape; the 16x16 build keeps MFMA
+# accumulators in VGPRs so that the per-plane lane shift needs no copies.
+VARIANTS = {
+    "vkt_filter_mfma.hip": [
+        ("vkt_filter_mfma16", ["-DVKT_MFMA_SHAPE=16", "-mllvm", "--amdgpu-mfma-vgpr-form"]),
+        ("vkt_filter_mfma32", ["-DVKT_MFMA_SHAPE=32"]),
+    ],
+}
+
+
 def sources():
-    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
-                  if f.endswith(".hip"))
+    """(source, object stem, extra flags) for every object of the library."""
+    out = []
+    for f in sorted(os.listdir(CSRC)):
+        if not f.endswith(".hip"):
+            continue
+        for stem, extra in VARIANTS.get(f, [(f[:-4], [])]):
+            out.append((os.path.join(CSRC, f), stem, extra))
+    return out
 
 
-def _compile(src, verbose):
-    obj = os.path.join(OUT, os.path.basename(src)[:-4] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+def _compile(unit, verbose):
+    src, stem, extra = unit
+    obj = os.path.join(OUT, stem + ".o")
+    cmd = [HIPCC, *FLAGS, *extra, "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -44,10 +62,10 @@ def _compile(src, verbose):
 def build_lib(verbose: bool = False, jobs: int = 0) -> str:
     """Always recompile every translation unit and relink."""
     os.makedirs(OUT, exist_ok=True)
-    srcs = sources()
-    jobs = jobs or min(len(srcs), os.cpu_count() or 1, 8)
+    units = sources()
+    jobs = jobs or min(len(units), os.cpu_count() or 1, 8)
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
+        objs = list(ex.map(lambda u: _compile(u, verbose), units))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *objs]
     if verbose:

@@ -13,32 +13,12 @@
 
 #include "vkt_internal.h"
 
-struct vktStructuredVolume_ {
-    int32_t dims[3];
-    vktDataFormat fmt;
-    float cell[3];
-    float lo, hi;
-    void* dev;
-    bool owned;
-    int device;
-};
-
-struct vktFilter_ {
-    int32_t k;
-    bool is_int;
-    int32_t divisor;
-    int64_t sum_abs_int;        // sum |w| for integer filters
-    float wscale;               // power of two: max|w| * wscale in [2^14, 2^15)
-    float* d_wf;                // device float weights (k^3)
-    int32_t* d_wi;              // device int weights (k^3), integer filters
-    int device;
-};
-
 namespace {
 
 struct ThreadState {
     hipStream_t stream = nullptr;
     vktPrecision precision = vktPrecisionAuto;
+    bool autotune = false;
     bool init = false;
 };
 thread_local ThreadState t_state;
@@ -52,6 +32,7 @@ ThreadState& state()
             else if (!std::strcmp(p, "splitbf16")) t_state.precision = vktPrecisionSplitBF16;
             else if (!std::strcmp(p, "splitbf16x6")) t_state.precision = vktPrecisionSplitBF16x6;
         }
+        if (const char* p = std::getenv("VKT_AUTOTUNE")) t_state.autotune = p[0] == '1';
     }
     return t_state;
 }
@@ -60,24 +41,11 @@ ThreadState& state()
 // dereferenced.
 std::mutex g_mu;
 std::unordered_set<const void*> g_volumes, g_filters;
+uint64_t g_filter_serial = 0;
 
-bool live_volume(const vktStructuredVolume_* v)
-{
-    std::lock_guard<std::mutex> lk(g_mu);
-    return v && g_volumes.count(v);
-}
-bool live_filter(const vktFilter_* f)
-{
-    std::lock_guard<std::mutex> lk(g_mu);
-    return f && g_filters.count(f);
-}
-
-vktError from_hip(hipError_t e)
-{
-    if (e == hipSuccess) return vktNoError;
-    if (e == hipErrorOutOfMemory) return vktOutOfMemory;
-    return vktDeviceError;
-}
+using vkt::from_hip;
+using vkt::live_filter;
+using vkt::live_volume;
 
 bool valid_format(int f) { return f >= vktDataFormatUInt8 && f <= vktDataFormatFloat32; }
 
@@ -180,7 +148,7 @@ vktError create_filter(vktFilter* out, int32_t k, const float* wf, const int32_t
         wscale = std::ldexp(1.f, 15 - ex);     // amax * wscale in [2^14, 2^15)
     }
     auto* f = new (std::nothrow) vktFilter_{k, wi != nullptr, wi ? divisor : 1, sum_abs,
-                                            wscale, dwf, dwi, device};
+                                            wscale, 0, dwf, dwi, device};
     if (!f) {
         (void)hipFree(dwf);
         if (dwi) (void)hipFree(dwi);
@@ -188,6 +156,7 @@ vktError create_filter(vktFilter* out, int32_t k, const float* wf, const int32_t
     }
     {
         std::lock_guard<std::mutex> lk(g_mu);
+        f->serial = ++g_filter_serial;
         g_filters.insert(f);
     }
     *out = f;
@@ -197,6 +166,121 @@ vktError create_filter(vktFilter* out, int32_t k, const float* wf, const int32_t
 }  // namespace
 
 namespace vkt {
+
+bool live_volume(const vktStructuredVolume_* v)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    return v && g_volumes.count(v);
+}
+
+bool live_filter(const vktFilter_* f)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    return f && g_filters.count(f);
+}
+
+vktError from_hip(hipError_t e)
+{
+    if (e == hipSuccess) return vktNoError;
+    if (e == hipErrorOutOfMemory) return vktOutOfMemory;
+    return vktDeviceError;
+}
+
+hipStream_t thread_stream() { return state().stream; }
+vktPrecision thread_precision() { return state().precision; }
+bool thread_autotune() { return state().autotune; }
+
+VolDesc make_desc(const FilterJob& j, int tz, ClassGeom g)
+{
+    VolDesc a{};
+    a.src = j.src;
+    a.dst = j.dst;
+    a.X = j.X;
+    a.Y = j.Y;
+    a.Z = j.Z;
+    a.mode = j.mode;
+    a.tz = tz;
+    a.tiles_x = (j.X + g.tx - 1) / g.tx;
+    a.tiles_y = (j.Y + g.ty - 1) / g.ty;
+    a.woff = 0;
+    if (j.fmt == vktDataFormatFloat32) a.epi = j.int_filter ? kEpiFloatDiv : kEpiFloat;
+    else a.epi = j.int_filter ? kEpiIntDiv : kEpiRound;
+    a.D = j.D;
+    a.div2D = j.div2D;
+    a.inv_D = j.inv_D;
+    a.vec_ok = j.vec_store ? 1 : 0;
+    a.wscale = j.fmt == vktDataFormatFloat32 ? 1.0f : j.wscale;  // bf16 pieces are unscaled
+    a.unscale = 1.0f / a.wscale;
+    return a;
+}
+
+vktError build_job(const vktStructuredVolume_* dst, const vktStructuredVolume_* src,
+                   const vktFilter_* filt, int mode, vktPrecision prec, FilterJob& j,
+                   bool& mfma, bool& six)
+{
+    if (!live_volume(dst) || !live_volume(src) || !live_filter(filt)) return vktInvalidValue;
+    if (mode < vktAddressModeClamp || mode > vktAddressModeBorder) return vktInvalidValue;
+    if (dst->fmt != src->fmt) return vktInvalidValue;
+    for (int a = 0; a < 3; ++a)
+        if (dst->dims[a] != src->dims[a]) return vktInvalidValue;
+    const int64_t bytes = cells(src) * cell_bytes(src->fmt);
+    const char* d0 = static_cast<const char*>(dst->dev);
+    const char* s0 = static_cast<const char*>(src->dev);
+    if (d0 < s0 + bytes && s0 < d0 + bytes) return vktInvalidValue;  // overlap
+    // in-plane byte offsets are 32-bit in the kernels
+    if ((int64_t)src->dims[0] * src->dims[1] * cell_bytes(src->fmt) >= (int64_t(1) << 31))
+        return vktUnsupported;
+
+    j = FilterJob{};
+    j.src = src->dev;
+    j.dst = dst->dev;
+    j.X = src->dims[0];
+    j.Y = src->dims[1];
+    j.Z = src->dims[2];
+    j.mode = mode;
+    j.fmt = src->fmt;
+    j.k = filt->k;
+    j.wf = filt->d_wf;
+    j.wi = filt->d_wi;
+    j.int_filter = filt->is_int;
+    j.D = filt->divisor;
+    j.inv_D = 1.0f / (float)filt->divisor;
+    j.int_acc = false;
+    if (filt->is_int && src->fmt != vktDataFormatFloat32) {
+        const int64_t mx = src->fmt == vktDataFormatUInt8 ? 255 : 65535;
+        if (filt->sum_abs_int * mx > (int64_t(1) << 30)) return vktUnsupported;
+        // FP32 sums of integer products are exact while |partial sums| < 2^24;
+        // beyond that the kernel accumulates in int32.
+        j.int_acc = filt->sum_abs_int * mx >= (int64_t(1) << 24);
+        j.div2D = make_udiv(2u * (uint32_t)filt->divisor);
+    }
+    j.vec_store = (j.X % 4 == 0) &&
+                  (reinterpret_cast<uintptr_t>(dst->dev) % (4 * cell_bytes(src->fmt)) == 0);
+    j.wscale = filt->wscale;
+    // Plan: float-weight filters with k >= 5 run on the matrix cores unless
+    // the precision is FP32; everything else (k < 5, integer weights, whose
+    // results are exact integers) runs on the vector ALUs.
+    mfma = !filt->is_int && filt->k >= 5 && prec != vktPrecisionFP32;
+    // float32 cells: the 6-product split keeps every product term down to
+    // 2^-16 relative (about 1e-7 after rounding); Auto uses it.  The 3-product
+    // split drops three terms of up to 2^-16 each and is opt-in.
+    six = prec == vktPrecisionSplitBF16x6 || prec == vktPrecisionAuto;
+    return vktNoError;
+}
+
+hipError_t launch_filter_mfma(const FilterJob& j, bool six_products, hipStream_t s)
+{
+    return j.k <= 7 ? launch_filter_mfma_s16(j, six_products, s)
+                    : launch_filter_mfma_s32(j, six_products, s);
+}
+
+const void* mfma_batched_kernel(vktDataFormat f, int k, bool six_products)
+{
+    return k <= 7 ? mfma_batched_kernel_s16(f, k, six_products)
+                  : mfma_batched_kernel_s32(f, k, six_products);
+}
+
+ClassGeom mfma_geom(int k) { return k <= 7 ? mfma_geom_s16(k) : mfma_geom_s32(k); }
 
 UDiv make_udiv(uint32_t d)
 {
@@ -328,54 +412,18 @@ vktError vktFillRangeSV(vktStructuredVolume v, int32_t x0, int32_t y0, int32_t z
 vktError vktApplyFilter(vktStructuredVolume dst, vktStructuredVolume src, vktFilter filt,
                         vktAddressMode mode)
 {
-    if (!live_volume(dst) || !live_volume(src) || !live_filter(filt)) return vktInvalidValue;
-    if (mode < vktAddressModeClamp || mode > vktAddressModeBorder) return vktInvalidValue;
-    if (dst->fmt != src->fmt) return vktInvalidValue;
-    for (int a = 0; a < 3; ++a)
-        if (dst->dims[a] != src->dims[a]) return vktInvalidValue;
-    const int64_t bytes = cells(src) * vkt::cell_bytes(src->fmt);
-    const char* d0 = static_cast<const char*>(dst->dev);
-    const char* s0 = static_cast<const char*>(src->dev);
-    if (d0 < s0 + bytes && s0 < d0 + bytes) return vktInvalidValue;  // overlap
-    // in-plane byte offsets are 32-bit in the kernels
-    if ((int64_t)src->dims[0] * src->dims[1] * vkt::cell_bytes(src->fmt) >= (int64_t(1) << 31))
-        return vktUnsupported;
-
-    vkt::FilterJob j{};
-    j.src = src->dev;
-    j.dst = dst->dev;
-    j.X = src->dims[0];
-    j.Y = src->dims[1];
-    j.Z = src->dims[2];
-    j.mode = mode;
-    j.fmt = src->fmt;
-    j.k = filt->k;
-    j.wf = filt->d_wf;
-    j.wi = filt->d_wi;
-    j.int_filter = filt->is_int;
-    j.D = filt->divisor;
-    j.inv_D = 1.0f / (float)filt->divisor;
-    j.int_acc = false;
-    if (filt->is_int && src->fmt != vktDataFormatFloat32) {
-        const int64_t mx = src->fmt == vktDataFormatUInt8 ? 255 : 65535;
-        if (filt->sum_abs_int * mx > (int64_t(1) << 30)) return vktUnsupported;
-        // FP32 sums of integer products are exact while |partial sums| < 2^24;
-        // beyond that the kernel accumulates in int32.
-        j.int_acc = filt->sum_abs_int * mx >= (int64_t(1) << 24);
-        j.div2D = vkt::make_udiv(2u * (uint32_t)filt->divisor);
-    }
-    j.vec_store = (j.X % 4 == 0) &&
-                  (reinterpret_cast<uintptr_t>(dst->dev) % (4 * vkt::cell_bytes(src->fmt)) == 0);
-    j.wscale = filt->wscale;
-    // Plan: float-weight filters with k >= 5 run on the matrix cores unless
-    // the thread asks for FP32; everything else (k < 5, integer weights,
-    // whose results are exact integers) runs on the vector ALUs.
-    const vktPrecision prec = state().precision;
-    const bool mfma = !filt->is_int && filt->k >= 5 && prec != vktPrecisionFP32;
-    if (mfma)
-        return from_hip(vkt::launch_filter_mfma(j, prec == vktPrecisionSplitBF16x6,
-                                                state().stream));
+    vkt::FilterJob j;
+    bool mfma = false, six = false;
+    const vktError e = vkt::build_job(dst, src, filt, mode, state().precision, j, mfma, six);
+    if (e != vktNoError) return e;
+    if (mfma) return from_hip(vkt::launch_filter_mfma(j, six, state().stream));
     return from_hip(vkt::launch_filter_valu(j, state().stream));
+}
+
+vktError vktSetAutotune(int enable)
+{
+    state().autotune = enable != 0;
+    return vktNoError;
 }
 
 vktError vktSetStream(void* stream)

@@ -1,0 +1,463 @@
+// vkt_batch.hip -- vktApplyFilterBatched: many independent ApplyFilter calls
+// of uneven volume sizes and mixed filter sizes in persistent launches.
+//
+// Planning (host, once per distinct batch):
+//   * every (dst, src, filter) triple is validated and planned exactly as by
+//     vktApplyFilter; triples fall into arithmetic classes (cell format, k,
+//     vector-ALU or matrix-core path and its variant), one persistent kernel
+//     per class;
+//   * each volume is cut into tile-slabs (the kernels' output tiles times a
+//     z-slab depth chosen per class and batch size class, optionally by the
+//     autotuner); the class's work list is sorted longest first;
+//   * descriptors, work lists, the classes' weight pools and the work-queue
+//     counters go to one device buffer; the class kernels become parallel
+//     kernel nodes of one hipGraph.
+// Launch: one hipGraphLaunch on the calling thread's stream.  Plans are cached
+// by the batch's signature (pointers, dims, formats, filter identities, mode,
+// precision, stream), so repeated batches replay the instantiated graph.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "vkt_internal.h"
+
+namespace vkt {
+namespace {
+
+struct ClassKey {
+    int fmt, k, path, flag;  // path 0 = vector ALU (flag: int accumulate), 1 = matrix (flag: 6 products)
+    bool operator<(const ClassKey& o) const
+    {
+        return std::tie(fmt, k, path, flag) < std::tie(o.fmt, o.k, o.path, o.flag);
+    }
+};
+
+const void* class_kernel(const ClassKey& c)
+{
+    return c.path ? mfma_batched_kernel((vktDataFormat)c.fmt, c.k, c.flag != 0)
+                  : valu_batched_kernel((vktDataFormat)c.fmt, c.k, c.flag != 0);
+}
+
+ClassGeom class_geom(const ClassKey& c) { return c.path ? mfma_geom(c.k) : valu_geom(c.k); }
+
+// ---- tuning table: (class, size class) -> z-slab depth ---------------------
+
+struct TuneKey {
+    ClassKey c;
+    int size_class;
+    bool operator<(const TuneKey& o) const
+    {
+        return std::tie(c, size_class) < std::tie(o.c, o.size_class);
+    }
+};
+
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;
+bool g_tune_loaded = false;
+
+// Size class of a set of volumes: log2 of the mean cube-root edge length.
+int size_class_of(const std::vector<FilterJob>& jobs)
+{
+    double s = 0;
+    for (const auto& j : jobs) s += std::cbrt((double)j.X * j.Y * j.Z);
+    return jobs.empty() ? 0 : (int)std::floor(std::log2(s / (double)jobs.size()));
+}
+
+void tune_load_locked()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = std::getenv("VKT_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    TuneKey k;
+    int tz;
+    while (std::fscanf(f, "%d %d %d %d %d %d", &k.c.fmt, &k.c.k, &k.c.path, &k.c.flag,
+                       &k.size_class, &tz) == 6)
+        g_tune[k] = tz;
+    std::fclose(f);
+}
+
+void tune_store_locked()
+{
+    const char* path = std::getenv("VKT_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = std::fopen(path, "w");
+    if (!f) return;
+    for (const auto& e : g_tune)
+        std::fprintf(f, "%d %d %d %d %d %d\n", e.first.c.fmt, e.first.c.k, e.first.c.path,
+                     e.first.c.flag, e.first.size_class, e.second);
+    std::fclose(f);
+}
+
+int default_tz(const ClassKey& c, const ClassGeom& g)
+{
+    (void)c;
+    return std::max(g.tz_min, 16);
+}
+
+// ---- plans ------------------------------------------------------------------
+
+struct ClassPlan {
+    ClassKey key;
+    const void* func = nullptr;
+    std::vector<int> members;      // indices into the batch
+    int tz = 0;
+    unsigned grid = 0;
+    BatchArgs args{};
+    // offsets inside the plan's device buffer
+    size_t off_desc = 0, off_items = 0, off_cnt = 0, off_wf = 0, off_wi = 0;
+    uint32_t nitems = 0;
+};
+
+struct Plan {
+    std::vector<uintptr_t> sig;
+    int device = 0;
+    char* dbuf = nullptr;
+    size_t dbytes = 0;
+    std::vector<ClassPlan> classes;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~Plan()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (dbuf) (void)hipFree(dbuf);
+    }
+};
+
+std::mutex g_plan_mu;
+std::vector<std::unique_ptr<Plan>> g_plans;  // most recent last
+constexpr size_t kMaxPlans = 16;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Work list of one class at slab depth tz, longest items first.
+std::vector<WorkItem> make_items(const std::vector<VolDesc>& descs,
+                                 const std::vector<int>& members, int k)
+{
+    struct Costed {
+        WorkItem w;
+        int64_t cost;
+    };
+    std::vector<Costed> v;
+    for (size_t m = 0; m < members.size(); ++m) {
+        const VolDesc& a = descs[m];
+        const int64_t nt = (int64_t)a.tiles_x * a.tiles_y;
+        const int slabs = (a.Z + a.tz - 1) / a.tz;
+        for (int sl = 0; sl < slabs; ++sl) {
+            const int planes = std::min(a.tz, a.Z - sl * a.tz) + k - 1;
+            for (int64_t t = 0; t < nt; ++t) {
+                Costed c;
+                c.w.vol = (uint32_t)m;
+                c.w.lid = (uint32_t)(sl * nt + t);
+                c.cost = planes;
+                v.push_back(c);
+            }
+        }
+    }
+    std::stable_sort(v.begin(), v.end(),
+                     [](const Costed& a, const Costed& b) { return a.cost > b.cost; });
+    std::vector<WorkItem> out(v.size());
+    for (size_t i = 0; i < v.size(); ++i) out[i] = v[i].w;
+    return out;
+}
+
+struct Triple {
+    FilterJob j;
+    ClassKey key;
+    const vktFilter_* f;
+};
+
+// Build (or rebuild for another slab depth) the host-side arrays of one class.
+void class_arrays(const std::vector<Triple>& tr, ClassPlan& cp, std::vector<VolDesc>& descs,
+                  std::vector<WorkItem>& items, std::vector<float>& wf,
+                  std::vector<int32_t>& wi)
+{
+    const ClassGeom g = class_geom(cp.key);
+    descs.clear();
+    wf.clear();
+    wi.clear();
+    std::map<uint64_t, uint32_t> woff;  // filter serial -> pool offset
+    const int n3 = cp.key.k * cp.key.k * cp.key.k;
+    for (int idx : cp.members) {
+        const Triple& t = tr[idx];
+        VolDesc a = make_desc(t.j, std::min(cp.tz, t.j.Z), g);
+        auto it = woff.find(t.f->serial);
+        if (it == woff.end()) {
+            const uint32_t off = (uint32_t)wf.size();
+            wf.resize(wf.size() + n3);
+            wi.resize(wi.size() + n3);
+            it = woff.emplace(t.f->serial, off).first;
+        }
+        a.woff = it->second;
+        descs.push_back(a);
+    }
+    items = make_items(descs, cp.members, cp.key.k);
+}
+
+// Device copies of the weights go into the pools with device-to-device
+// copies (the filters' weights live on the device).
+hipError_t upload_class(const std::vector<Triple>& tr, ClassPlan& cp, char* base,
+                        const std::vector<VolDesc>& descs, const std::vector<WorkItem>& items)
+{
+    hipError_t e = hipMemcpy(base + cp.off_desc, descs.data(), descs.size() * sizeof(VolDesc),
+                             hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(base + cp.off_items, items.data(), items.size() * sizeof(WorkItem),
+                      hipMemcpyHostToDevice);
+    const int n3 = cp.key.k * cp.key.k * cp.key.k;
+    for (size_t m = 0; m < cp.members.size() && e == hipSuccess; ++m) {
+        const vktFilter_* f = tr[cp.members[m]].f;
+        const uint32_t off = descs[m].woff;
+        e = hipMemcpy(base + cp.off_wf + off * sizeof(float), f->d_wf, n3 * sizeof(float),
+                      hipMemcpyDeviceToDevice);
+        if (e == hipSuccess && f->d_wi)
+            e = hipMemcpy(base + cp.off_wi + off * sizeof(int32_t), f->d_wi,
+                          n3 * sizeof(int32_t), hipMemcpyDeviceToDevice);
+    }
+    cp.nitems = (uint32_t)items.size();
+    cp.args.vols = reinterpret_cast<const VolDesc*>(base + cp.off_desc);
+    cp.args.items = reinterpret_cast<const WorkItem*>(base + cp.off_items);
+    cp.args.nitems = cp.nitems;
+    cp.args.counters = reinterpret_cast<uint32_t*>(base + cp.off_cnt);
+    cp.args.wpool = reinterpret_cast<const float*>(base + cp.off_wf);
+    cp.args.wipool = reinterpret_cast<const int32_t*>(base + cp.off_wi);
+    return e;
+}
+
+hipError_t launch_class(const ClassPlan& cp, hipStream_t s)
+{
+    BatchArgs a = cp.args;
+    void* params[] = {&a};
+    return hipLaunchKernel(cp.func, dim3(cp.grid), dim3(256), params, 0, s);
+}
+
+// Time one class alone at a given slab depth (two launches on the caller's
+// stream, the second timed; waits for both).
+float time_class(const std::vector<Triple>& tr, ClassPlan& cp, char* base, int tz,
+                 hipStream_t s)
+{
+    cp.tz = tz;
+    std::vector<VolDesc> descs;
+    std::vector<WorkItem> items;
+    std::vector<float> wf;
+    std::vector<int32_t> wi;
+    class_arrays(tr, cp, descs, items, wf, wi);
+    if (upload_class(tr, cp, base, descs, items) != hipSuccess) return -1.f;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1.f;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return -1.f;
+    }
+    float ms = -1.f;
+    if (launch_class(cp, s) == hipSuccess && hipEventRecord(e0, s) == hipSuccess &&
+        launch_class(cp, s) == hipSuccess && hipEventRecord(e1, s) == hipSuccess &&
+        hipEventSynchronize(e1) == hipSuccess)
+        (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ms;
+}
+
+vktError build_plan(const std::vector<Triple>& tr, std::vector<uintptr_t>&& sig, bool tune,
+                    hipStream_t stream, Plan*& out)
+{
+    auto plan = std::make_unique<Plan>();
+    plan->sig = std::move(sig);
+    if (hipGetDevice(&plan->device) != hipSuccess) return vktDeviceError;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, plan->device) !=
+        hipSuccess)
+        return vktDeviceError;
+
+    std::map<ClassKey, std::vector<int>> groups;
+    for (size_t i = 0; i < tr.size(); ++i) groups[tr[i].key].push_back((int)i);
+
+    // size the device buffer with the smallest slab depth any candidate uses
+    // (most items), so tuning and the final plan fit
+    size_t bytes = 0;
+    for (auto& g : groups) {
+        ClassPlan cp;
+        cp.key = g.first;
+        cp.members = g.second;
+        cp.func = class_kernel(cp.key);
+        if (!cp.func) return vktUnsupported;
+        const ClassGeom geom = class_geom(cp.key);
+        size_t nitems = 0;
+        for (int idx : cp.members) {
+            const FilterJob& j = tr[idx].j;
+            const int tzmin = std::min(geom.tz_min, j.Z);
+            nitems += (size_t)((j.X + geom.tx - 1) / geom.tx) * ((j.Y + geom.ty - 1) / geom.ty) *
+                      ((j.Z + tzmin - 1) / tzmin);
+        }
+        const size_t n3 = (size_t)cp.key.k * cp.key.k * cp.key.k;
+        cp.off_desc = bytes = align_up(bytes, 256);
+        bytes += cp.members.size() * sizeof(VolDesc);
+        cp.off_items = bytes = align_up(bytes, 256);
+        bytes += nitems * sizeof(WorkItem);
+        cp.off_cnt = bytes = align_up(bytes, 256);
+        bytes += 2 * sizeof(uint32_t);
+        cp.off_wf = bytes = align_up(bytes, 256);
+        bytes += cp.members.size() * n3 * sizeof(float);
+        cp.off_wi = bytes = align_up(bytes, 256);
+        bytes += cp.members.size() * n3 * sizeof(int32_t);
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, cp.func, 256, 0) !=
+                hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        cp.grid = (unsigned)(per_cu * cus);
+        plan->classes.push_back(cp);
+    }
+    plan->dbytes = bytes;
+    hipError_t e = hipMalloc(&plan->dbuf, bytes);
+    if (e != hipSuccess) return from_hip(e);
+    e = hipMemset(plan->dbuf, 0, bytes);  // queue counters start at zero
+    if (e != hipSuccess) return from_hip(e);
+
+    std::vector<FilterJob> jobs;
+    for (auto& cp : plan->classes) {
+        const ClassGeom geom = class_geom(cp.key);
+        jobs.clear();
+        for (int idx : cp.members) jobs.push_back(tr[idx].j);
+        const TuneKey tk{cp.key, size_class_of(jobs)};
+        int tz = 0;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            tune_load_locked();
+            auto it = g_tune.find(tk);
+            if (it != g_tune.end()) tz = it->second;
+        }
+        if (tz == 0 && tune) {
+            // autotune: time candidate slab depths on the real batch
+            float best = -1.f;
+            for (int cand : {8, 16, 32, 64}) {
+                if (cand < geom.tz_min && cand != 64) continue;
+                const float ms = time_class(tr, cp, plan->dbuf, cand, stream);
+                if (ms > 0.f && (best < 0.f || ms < best)) {
+                    best = ms;
+                    tz = cand;
+                }
+            }
+            if (tz > 0) {
+                std::lock_guard<std::mutex> lk(g_tune_mu);
+                g_tune[tk] = tz;
+                tune_store_locked();
+            }
+        }
+        if (tz == 0) tz = default_tz(cp.key, geom);
+        cp.tz = std::max(tz, geom.tz_min);
+        std::vector<VolDesc> descs;
+        std::vector<WorkItem> items;
+        std::vector<float> wf;
+        std::vector<int32_t> wi;
+        class_arrays(tr, cp, descs, items, wf, wi);
+        e = upload_class(tr, cp, plan->dbuf, descs, items);
+        if (e != hipSuccess) return from_hip(e);
+        if (cp.grid > cp.nitems) cp.grid = cp.nitems > 0 ? cp.nitems : 1;
+    }
+
+    // one graph: the class kernels as independent (parallel) kernel nodes
+    e = hipGraphCreate(&plan->graph, 0);
+    for (auto& cp : plan->classes) {
+        if (e != hipSuccess) break;
+        hipKernelNodeParams p{};
+        void* params[] = {&cp.args};
+        p.func = const_cast<void*>(cp.func);
+        p.gridDim = dim3(cp.grid);
+        p.blockDim = dim3(256);
+        p.sharedMemBytes = 0;
+        p.kernelParams = params;
+        p.extra = nullptr;
+        hipGraphNode_t node;
+        e = hipGraphAddKernelNode(&node, plan->graph, nullptr, 0, &p);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return from_hip(e);
+
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    if (g_plans.size() >= kMaxPlans) g_plans.erase(g_plans.begin());  // hipFree waits
+    g_plans.push_back(std::move(plan));
+    out = g_plans.back().get();
+    return vktNoError;
+}
+
+}  // namespace
+}  // namespace vkt
+
+extern "C" {
+
+vktError vktApplyFilterBatched(int32_t n, const vktStructuredVolume* dst,
+                               const vktStructuredVolume* src, const vktFilter* filters,
+                               vktAddressMode mode)
+{
+    using namespace vkt;
+    if (n < 0 || (n > 0 && (!dst || !src || !filters))) return vktInvalidValue;
+    if (n == 0) return vktNoError;
+    const vktPrecision prec = thread_precision();
+    hipStream_t stream = thread_stream();
+    std::vector<Triple> tr(n);
+    std::vector<uintptr_t> sig;
+    sig.reserve(4 + 6 * (size_t)n);
+    sig.push_back((uintptr_t)n);
+    sig.push_back((uintptr_t)mode);
+    sig.push_back((uintptr_t)prec);
+    sig.push_back((uintptr_t)stream);
+    for (int i = 0; i < n; ++i) {
+        bool mfma = false, six = false;
+        const vktError e = build_job(dst[i], src[i], filters[i], mode, prec, tr[i].j, mfma, six);
+        if (e != vktNoError) return e;
+        const FilterJob& j = tr[i].j;
+        tr[i].f = filters[i];
+        tr[i].key = ClassKey{(int)j.fmt, j.k, mfma ? 1 : 0, mfma ? (six ? 1 : 0) : (j.int_acc ? 1 : 0)};
+        sig.push_back((uintptr_t)j.src);
+        sig.push_back((uintptr_t)j.dst);
+        sig.push_back((uintptr_t)filters[i]->serial);
+        sig.push_back((uintptr_t)j.X);
+        sig.push_back((uintptr_t)j.Y);
+        sig.push_back((uintptr_t)j.Z | ((uintptr_t)j.fmt << 40));
+    }
+    // outputs must not overlap any volume of the batch (they run concurrently)
+    std::vector<std::pair<uintptr_t, uintptr_t>> dr, sr;
+    for (int i = 0; i < n; ++i) {
+        const uintptr_t b = (uintptr_t)cell_bytes(tr[i].j.fmt) * tr[i].j.X * tr[i].j.Y * tr[i].j.Z;
+        dr.push_back({(uintptr_t)tr[i].j.dst, (uintptr_t)tr[i].j.dst + b});
+        sr.push_back({(uintptr_t)tr[i].j.src, (uintptr_t)tr[i].j.src + b});
+    }
+    std::vector<std::pair<uintptr_t, uintptr_t>> all = sr;
+    std::sort(dr.begin(), dr.end());
+    for (size_t i = 1; i < dr.size(); ++i)
+        if (dr[i].first < dr[i - 1].second) return vktInvalidValue;
+    for (const auto& d : dr)
+        for (const auto& s : all)
+            if (d.first < s.second && s.first < d.second) return vktInvalidValue;
+
+    Plan* plan = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        for (auto it = g_plans.begin(); it != g_plans.end(); ++it)
+            if ((*it)->sig == sig && (*it)->device == dev) {
+                plan = it->get();
+                break;
+            }
+    }
+    if (!plan) {
+        const vktError e = build_plan(tr, std::move(sig), thread_autotune(), stream, plan);
+        if (e != vktNoError) return e;
+    }
+    return from_hip(hipGraphLaunch(plan->exec, stream));
+}
+
+}  // extern "C"

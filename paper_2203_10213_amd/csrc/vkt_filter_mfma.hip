@@ -1,14 +1,16 @@
 // vkt_filter_mfma.hip -- ApplyFilter for filters of size k >= 5 on the
 // matrix cores: an implicit GEMM with split 16-bit operands and FP32
-// accumulation.
+// accumulation.  This file is compiled twice: with VKT_MFMA_SHAPE=16 for
+// k <= 7 (16x16x32 tiles, accumulators in VGPRs) and with VKT_MFMA_SHAPE=32
+// for k >= 9 (32x32x16 tiles).
 //
 // Operation (paper Sec. 3.2 "Volume Manipulation"; benchmarked as a Gaussian
 // blur, Sec. 4.3):
 //   T(x,y,z) = sum_{a,b,c} w[a + k(b + k c)] * s(A(x+a-r), A(y+b-r), A(z+c-r)).
 //
-// GEMM embedding, per input plane zi (D += A * B on 16x16x32 or 32x32x16
-// MFMA tiles):
-//   M (rows i)    : consecutive output rows y_i of one x-strip,
+// GEMM embedding, per input plane zi (D += A * B on MFMA tiles):
+//   M (rows i)    : consecutive output rows y_i of one x-strip of NX = 2
+//                   output columns,
 //   K (reduction) : (filter row b, input column ax) pairs; the A operand is
 //                   the input window s(x_s - r + ax, y_i + b - r, zi), read
 //                   straight from the LDS-staged plane (no im2col copy),
@@ -20,6 +22,12 @@
 // live side by side in D (a z ring).  After each input plane the group
 // c = k-1 holds a finished output plane; it is stored and the columns shift
 // by NX lanes (group c -> c+1, group 0 restarts at zero).
+//
+// The four x-strips a wave owns are adjacent, so one 32-byte LDS read per
+// (row block, K chunk, operand piece) holds all four strips' 16-byte windows
+// (at dword offsets 0..3).  Finished outputs leave through raw buffer stores:
+// lanes that hold no finished output, and cells past the volume's edge, get
+// an out-of-range offset and their store is discarded.
 //
 // Split precision (16-bit operands, exact FP32 products, FP32 sums):
 //   uint8   voxels: exact in fp16 (1 piece) x weights in 2 fp16 pieces;
@@ -34,28 +42,33 @@
 
 #include <type_traits>
 
+#ifndef VKT_MFMA_SHAPE
+#error "compile with -DVKT_MFMA_SHAPE=16 or 32"
+#endif
+
 namespace vkt {
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kNT = 256;                     // threads per workgroup (4 waves)
 constexpr uint32_t kRsrcWord3 = 0x00020000u; // gfx9-family raw buffer
-constexpr uint32_t kOutside = 0x80000000u;   // byte offset that reads 0
+constexpr uint32_t kOutside = 0x80000000u;   // byte offset that is dropped / reads 0
 
-// MFMA tile shapes.  RPC = filter rows per K chunk, AXW = input columns per
-// filter row in the K dimension, NACC = accumulator registers per lane.
+// MFMA tile shapes.  AXW = input columns per filter row in the K dimension,
+// NACC = accumulator registers per lane.
 template <int SHAPE> struct Mf;
 template <> struct Mf<16> {
-    static constexpr int MT = 16, NT = 16, RPC = 4, AXW = 8, NACC = 4;
+    static constexpr int MT = 16, NT = 16, AXW = 8, NACC = 4;
     using acc_t = f32x4;
 };
 template <> struct Mf<32> {
-    static constexpr int MT = 32, NT = 32, RPC = 1, AXW = 16, NACC = 16;
+    static constexpr int MT = 32, NT = 32, AXW = 16, NACC = 16;
     using acc_t = f32x16;
 };
 
@@ -95,23 +108,20 @@ struct Cfg {
     static_assert(NX + K - 1 <= M::AXW, "x window exceeds the K slots");
     static constexpr int NCH = SHAPE == 16 ? (K + 3) / 4 : K;      // K chunks
     static constexpr int SX = 16;                                   // strips per workgroup
+    static constexpr int WS = 4;                                    // strips per wave
+    static_assert(SX == 4 * WS, "four waves");
     static constexpr int SY = SHAPE == 16 ? 4 : 2;                  // row blocks per workgroup
     static constexpr int TX = SX * NX, TY = SY * M::MT;             // 32 x 64 output tile
-    static constexpr int PITCH = SHAPE == 16 ? 40 : 48;             // >= NX*(SX-1) + AXW
-    static_assert(PITCH >= NX * (SX - 1) + M::AXW, "pitch too small");
+    // a lane's 8-column windows of the wave's WS strips span SEGN columns,
+    // read as NRD 16-byte pieces
+    static constexpr int SEGN = NX * (WS - 1) + 8;
+    static constexpr int NRD = (SEGN + 7) / 8;
+    static constexpr int PITCH = SHAPE == 16 ? 40 : 48;             // row pitch (cells)
+    static_assert(PITCH % 8 == 0, "16-byte aligned rows");
+    static_assert(NX * WS * 3 + (SHAPE == 16 ? 0 : 8) + 8 * NRD <= PITCH, "pitch too small");
     static constexpr int HY = TY + K - 1;                           // staged rows
     static constexpr int NE = (PITCH * HY + kNT - 1) / kNT;         // staged cells / thread
-    static constexpr int WS = SX / 4;                               // strips per wave
     static constexpr int MTW = WS * SY;                             // M tiles per wave
-};
-
-struct MfmaArgs {
-    int32_t X, Y, Z;
-    int32_t mode;
-    int32_t tz, tiles_x, tiles_y;
-    uint32_t nblocks;
-    float wscale;     // 2^s applied to weights before fp16 splitting (1 for bf16)
-    float unscale;    // 2^-s
 };
 
 __device__ inline int addr_map(int64_t i, int64_t n, int mode)
@@ -149,10 +159,7 @@ __device__ inline T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off)
     }
 }
 
-__device__ inline uint16_t f16_bits(float x)
-{
-    return __builtin_bit_cast(uint16_t, (_Float16)x);
-}
+__device__ inline uint16_t f16_bits(float x) { return __builtin_bit_cast(uint16_t, (_Float16)x); }
 __device__ inline float f16_val(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
 __device__ inline uint16_t bf16_bits(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
 __device__ inline float bf16_val(uint16_t h) { return (float)__builtin_bit_cast(__bf16, h); }
@@ -193,7 +200,7 @@ __device__ inline void split_weight(float w, float scale, uint16_t* p)
 }
 
 template <int SHAPE, bool F16>
-__device__ inline typename Mf<SHAPE>::acc_t mfma(u16x8 a, u16x8 b, typename Mf<SHAPE>::acc_t c)
+__device__ inline typename Mf<SHAPE>::acc_t mfma(u32x4 a, u16x8 b, typename Mf<SHAPE>::acc_t c)
 {
     if constexpr (SHAPE == 16) {
         if constexpr (F16)
@@ -229,21 +236,29 @@ __device__ inline float shift_cols(float v, int lane)
     }
 }
 
+// Store one finished value (every lane stores; dropped lanes carry an
+// out-of-range offset).
 template <typename T>
-__device__ inline T store_value(float t)
+__device__ inline void store_out(__amdgpu_buffer_rsrc_t r, uint32_t voff, int soff, float t,
+                                 float unscale)
 {
     if constexpr (std::is_same<T, float>::value) {
-        return t;
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(t * unscale), r, (int)voff, soff, 0);
     } else {
         constexpr float kMax = std::is_same<T, uint8_t>::value ? 255.f : 65535.f;
-        return (T)fminf(fmaxf(floorf(t + 0.5f), 0.f), kMax);
+        // floor(q + 1/2) saturated: truncation of a value clamped to [0, max]
+        const float q = __builtin_amdgcn_fmed3f(fmaf(t, unscale, 0.5f), 0.f, kMax);
+        const uint32_t u = (uint32_t)q;
+        if constexpr (sizeof(T) == 1)
+            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)u, r, (int)voff, soff, 0);
+        else
+            __builtin_amdgcn_raw_buffer_store_b16((uint16_t)u, r, (int)voff, soff, 0);
     }
 }
 
 template <class C>
-__global__ __launch_bounds__(kNT, 1) void filter_mfma_kernel(
-    const typename C::Tin* __restrict__ src, typename C::Tin* __restrict__ dst,
-    const float* __restrict__ w, MfmaArgs a)
+__device__ void mfma_tile(const VolDesc& a, const float* __restrict__ w, int tile, int slab,
+                          uint16_t* lds_base)
 {
     using T = typename C::Tin;
     using PC = typename C::PC;
@@ -254,15 +269,14 @@ __global__ __launch_bounds__(kNT, 1) void filter_mfma_kernel(
     constexpr int PM = std::is_same<T, uint8_t>::value ? kU8
                        : std::is_same<T, uint16_t>::value ? kU16
                        : (PC::NPROD == 6 ? kF32x6 : kF32x3);
-    __shared__ __align__(16) uint16_t lds[2][PC::PS][C::HY * C::PITCH];
+    auto lds = reinterpret_cast<uint16_t(*)[PC::PS][C::HY * C::PITCH]>(lds_base);
+    const T* __restrict__ src = static_cast<const T*>(a.src);
 
     const int t = threadIdx.x, lane = t % 64, wave = t / 64;
-    const uint32_t lid = xcd_remap(blockIdx.x, a.nblocks);
-    const uint32_t ntiles = (uint32_t)a.tiles_x * (uint32_t)a.tiles_y;
-    const int tile = (int)(lid % ntiles), slab = (int)(lid / ntiles);
     const int x0 = (tile % a.tiles_x) * C::TX, y0 = (tile / a.tiles_x) * C::TY;
     const int zb = slab * a.tz, ze = min(zb + a.tz, a.Z);
     const int64_t plane = (int64_t)a.X * a.Y;
+    const int32_t plane_bytes = (int32_t)(plane * (int64_t)sizeof(T));  // < 2^31 (host check)
 
     // ---- B operand: x-Toeplitz band of each filter row, split into pieces
     u16x8 B[C::NCH][PC::NBI];
@@ -297,13 +311,12 @@ __global__ __launch_bounds__(kNT, 1) void filter_mfma_kernel(
         const int gx = addr_map((int64_t)x0 - R + hx, a.X, a.mode);
         const int gy = addr_map((int64_t)y0 - R + hy, a.Y, a.mode);
         // cells past the volume edge that only feed zero weights still read a
-        // finite value: clamp mode fetches them, border mode reads zero
+        // finite value: clamp/wrap/mirror fetch them, border reads zero
         goff[i] = (gx < 0 || gy < 0)
                       ? kOutside
                       : ((uint32_t)gy * (uint32_t)a.X + (uint32_t)gx) * (uint32_t)sizeof(T);
         loff[i] = e;
     }
-    const int32_t plane_bytes = (int32_t)(plane * (int64_t)sizeof(T));
     uint16_t stage[C::NE][PC::PS];
     auto gather = [&](int zi) {
         const int gz = addr_map(zi, a.Z, a.mode);
@@ -321,6 +334,23 @@ __global__ __launch_bounds__(kNT, 1) void filter_mfma_kernel(
             for (int ps = 0; ps < PC::PS; ++ps) lds[buf][ps][loff[i]] = stage[i][ps];
     };
 
+    // ---- output offsets: lane's first finished row of each M tile, or kOutside
+    const int jcol = lane % M::NT;
+    const int xo = jcol - (K - 1) * C::NX;  // finished column group k-1
+    const int row0 = 4 * (lane / M::NT);
+    uint32_t ooff[C::MTW];
+#pragma unroll
+    for (int m = 0; m < C::MTW; ++m) {
+        const int strip = wave * C::WS + m % C::WS, yb = m / C::WS;
+        const int x = x0 + C::NX * strip + xo;
+        const int y = y0 + yb * M::MT + row0;
+        // rows past the volume's last row fall beyond the plane: dropped too
+        ooff[m] = (xo >= 0 && xo < C::NX && x < a.X)
+                      ? ((uint32_t)y * (uint32_t)a.X + (uint32_t)x) * (uint32_t)sizeof(T)
+                      : kOutside;
+    }
+    const int row_bytes = a.X * (int)sizeof(T);
+
     acc_t acc[C::MTW];
 #pragma unroll
     for (int m = 0; m < C::MTW; ++m)
@@ -329,6 +359,7 @@ __global__ __launch_bounds__(kNT, 1) void filter_mfma_kernel(
 
     // lane's A-operand coordinates inside an M tile
     const int ai = lane % M::MT, ag = lane / M::MT;
+    const int acol = C::NX * C::WS * wave + (C::SHAPE == 16 ? 0 : 8 * ag);
 
     const int zi_beg = zb - R, zi_end = ze + R;
     gather(zi_beg);
@@ -340,24 +371,34 @@ __global__ __launch_bounds__(kNT, 1) void filter_mfma_kernel(
         gather(min(zi + 1, zi_end - 1));
 
 #pragma unroll
-        for (int m = 0; m < C::MTW; ++m) {
-            const int strip = wave * C::WS + m % C::WS, yb = m / C::WS;
-            const int col = C::NX * strip + (C::SHAPE == 16 ? 0 : 8 * ag);
+        for (int yb = 0; yb < C::SY; ++yb) {
 #pragma unroll
             for (int q = 0; q < C::NCH; ++q) {
                 int b = C::SHAPE == 16 ? q * 4 + ag : q;
                 if (b > K - 1) b = K - 1;  // zero weights there; keep A finite
                 const int row = yb * M::MT + ai + b;
-                u16x8 A[PC::PS];
+                // one segment per piece holds the windows of the wave's strips
+                u32x4 seg[PC::PS][C::NRD];
 #pragma unroll
-                for (int ps = 0; ps < PC::PS; ++ps) {
-                    const uint16_t* p = &lds[cur][ps][row * C::PITCH + col];
-                    __builtin_memcpy(&A[ps], p, 16);  // 4-byte aligned 16-byte read
+                for (int ps = 0; ps < PC::PS; ++ps)
+#pragma unroll
+                    for (int h = 0; h < C::NRD; ++h)
+                        seg[ps][h] = *reinterpret_cast<const u32x4*>(
+                            &lds[cur][ps][row * C::PITCH + acol + 8 * h]);
+#pragma unroll
+                for (int s = 0; s < C::WS; ++s) {
+                    // strip s's window: dwords s .. s+3 of the segment
+                    u32x4 A[PC::PS];
+#pragma unroll
+                    for (int ps = 0; ps < PC::PS; ++ps)
+#pragma unroll
+                        for (int d = 0; d < 4; ++d)
+                            A[ps][d] = seg[ps][(s + d) / 4][(s + d) % 4];
+                    acc_t& c = acc[yb * C::WS + s];
+#pragma unroll
+                    for (int pr = 0; pr < PC::NPROD; ++pr)
+                        c = mfma<C::SHAPE, PC::F16>(A[PC::prod[pr][0]], B[q][PC::prod[pr][1]], c);
                 }
-#pragma unroll
-                for (int pr = 0; pr < PC::NPROD; ++pr)
-                    acc[m] = mfma<C::SHAPE, PC::F16>(A[PC::prod[pr][0]], B[q][PC::prod[pr][1]],
-                                                     acc[m]);
             }
         }
 
@@ -366,26 +407,16 @@ __global__ __launch_bounds__(kNT, 1) void filter_mfma_kernel(
         // ---- column group k-1 holds output plane zi - r
         const int zo = zi - R;
         if (zo >= zb) {
-            const int j = lane % M::NT;
-            const int xo = j - (K - 1) * C::NX;
-            if (xo >= 0 && xo < C::NX) {
-                T* orow = dst + (int64_t)zo * plane;
+            const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(
+                static_cast<char*>(a.dst) + (int64_t)zo * plane_bytes, (short)0, plane_bytes,
+                (int)kRsrcWord3);
 #pragma unroll
-                for (int m = 0; m < C::MTW; ++m) {
-                    const int strip = wave * C::WS + m % C::WS, yb = m / C::WS;
-                    const int x = x0 + C::NX * strip + xo;
-                    if (x < a.X) {
+            for (int m = 0; m < C::MTW; ++m)
 #pragma unroll
-                        for (int r = 0; r < M::NACC; ++r) {
-                            const int i = C::SHAPE == 16 ? 4 * (lane / 16) + r
-                                                         : 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
-                            const int y = y0 + yb * M::MT + i;
-                            if (y < a.Y)
-                                orow[(int64_t)y * a.X + x] = store_value<T>(acc[m][r] * a.unscale);
-                        }
-                    }
+                for (int r = 0; r < M::NACC; ++r) {
+                    const int drow = C::SHAPE == 16 ? r : 8 * (r / 4) + (r % 4);
+                    store_out<T>(rd, ooff[m], drow * row_bytes, acc[m][r], a.unscale);
                 }
-            }
         }
         // ---- advance the ring
 #pragma unroll
@@ -397,61 +428,131 @@ __global__ __launch_bounds__(kNT, 1) void filter_mfma_kernel(
 }
 
 template <class C>
-hipError_t launch_cfg(const FilterJob& j, float wscale, hipStream_t s)
+constexpr int lds_elems()
 {
-    MfmaArgs a{};
-    a.X = j.X;
-    a.Y = j.Y;
-    a.Z = j.Z;
-    a.mode = j.mode;
-    a.tiles_x = (j.X + C::TX - 1) / C::TX;
-    a.tiles_y = (j.Y + C::TY - 1) / C::TY;
-    const int64_t ntiles = (int64_t)a.tiles_x * a.tiles_y;
+    return 2 * C::PC::PS * C::HY * C::PITCH;
+}
+
+template <class C>
+__global__ __launch_bounds__(kNT, 1) void filter_mfma_kernel(VolDesc a,
+                                                             const float* __restrict__ w,
+                                                             uint32_t nblocks)
+{
+    __shared__ __align__(16) uint16_t lds[lds_elems<C>()];
+    const uint32_t lid = xcd_remap(blockIdx.x, nblocks);
+    const uint32_t ntiles = (uint32_t)a.tiles_x * (uint32_t)a.tiles_y;
+    mfma_tile<C>(a, w, (int)(lid % ntiles), (int)(lid / ntiles), lds);
+}
+
+// Persistent workgroups over a queue of (volume, tile-slab) items; the last
+// workgroup to finish resets the queue counters.
+template <class C>
+__global__ __launch_bounds__(kNT, 1) void filter_mfma_batched_kernel(BatchArgs b)
+{
+    __shared__ __align__(16) uint16_t lds[lds_elems<C>()];
+    __shared__ uint32_t s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(&b.counters[0], 1u);
+        __syncthreads();
+        const uint32_t it = s_item;
+        __syncthreads();
+        if (it >= b.nitems) break;
+        const WorkItem wi = b.items[it];
+        const VolDesc a = b.vols[wi.vol];
+        const uint32_t ntiles = (uint32_t)a.tiles_x * (uint32_t)a.tiles_y;
+        mfma_tile<C>(a, b.wpool + a.woff, (int)(wi.lid % ntiles), (int)(wi.lid / ntiles), lds);
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&b.counters[1], 1u) == gridDim.x - 1) {
+            atomicExch(&b.counters[0], 0u);
+            atomicExch(&b.counters[1], 0u);
+        }
+    }
+}
+
+#if VKT_MFMA_SHAPE == 16
+#define VKT_MFMA_KS(X) X(5) X(7)
+#define VKT_MFMA_FN(name) name##_s16
+#else
+#define VKT_MFMA_KS(X) X(9) X(11) X(13) X(15)
+#define VKT_MFMA_FN(name) name##_s32
+#endif
+
+ClassGeom geom_here(int k)
+{
+    using C = Cfg<float, VKT_MFMA_SHAPE == 16 ? 5 : 9, kF32x3>;
+    ClassGeom g;
+    g.tx = C::TX;
+    g.ty = C::TY;
+    g.tz_min = 4 * k;
+    return g;
+}
+
+template <class C>
+hipError_t launch_cfg(const FilterJob& j, hipStream_t s)
+{
+    const ClassGeom g = geom_here(j.k);
+    const int64_t ntiles = (int64_t)((j.X + g.tx - 1) / g.tx) * ((j.Y + g.ty - 1) / g.ty);
+    // z-slab depth: enough workgroups for several waves of the device, slabs
+    // deep enough that the k-1 ring warm-up planes cost little
     const int64_t want_slabs = (2048 + ntiles - 1) / ntiles;
     int tz = (int)((j.Z + want_slabs - 1) / want_slabs);
-    const int K = j.k;
-    const int tz_min = 4 * K;
-    if (tz < tz_min) tz = tz_min;
-    if (tz > 64) tz = 64;
+    if (tz < g.tz_min) tz = g.tz_min;
+    if (tz > 128) tz = 128;
     if (tz > j.Z) tz = j.Z;
-    a.tz = tz;
+    const VolDesc a = make_desc(j, tz, g);
     const int64_t nb = ntiles * ((j.Z + tz - 1) / tz);
     if (nb > 0x7fffffff) return hipErrorInvalidValue;
-    a.nblocks = (uint32_t)nb;
-    a.wscale = wscale;
-    a.unscale = 1.0f / wscale;
-    using T = typename C::Tin;
-    hipLaunchKernelGGL((filter_mfma_kernel<C>), dim3((unsigned)nb), dim3(kNT), 0, s,
-                       static_cast<const T*>(j.src), static_cast<T*>(j.dst), j.wf, a);
+    hipLaunchKernelGGL((filter_mfma_kernel<C>), dim3((unsigned)nb), dim3(kNT), 0, s, a, j.wf,
+                       (uint32_t)nb);
     return hipGetLastError();
 }
 
 template <typename T, int PM>
-hipError_t dispatch_k(const FilterJob& j, float wscale, hipStream_t s)
+hipError_t dispatch_k(const FilterJob& j, hipStream_t s)
 {
-    switch (j.k) {
-    case 5: return launch_cfg<Cfg<T, 5, PM>>(j, wscale, s);
-    case 7: return launch_cfg<Cfg<T, 7, PM>>(j, wscale, s);
-    case 9: return launch_cfg<Cfg<T, 9, PM>>(j, wscale, s);
-    case 11: return launch_cfg<Cfg<T, 11, PM>>(j, wscale, s);
-    case 13: return launch_cfg<Cfg<T, 13, PM>>(j, wscale, s);
-    case 15: return launch_cfg<Cfg<T, 15, PM>>(j, wscale, s);
-    }
+#define VKT_CASE(KK) \
+    case KK: return launch_cfg<Cfg<T, KK, PM>>(j, s);
+    switch (j.k) { VKT_MFMA_KS(VKT_CASE) }
+#undef VKT_CASE
     return hipErrorInvalidValue;
+}
+
+template <typename T, int PM>
+const void* batched_k(int k)
+{
+#define VKT_CASE(KK) \
+    case KK: return (const void*)&filter_mfma_batched_kernel<Cfg<T, KK, PM>>;
+    switch (k) { VKT_MFMA_KS(VKT_CASE) }
+#undef VKT_CASE
+    return nullptr;
 }
 
 }  // namespace
 
-hipError_t launch_filter_mfma(const FilterJob& j, bool six_products, hipStream_t s)
+ClassGeom VKT_MFMA_FN(mfma_geom)(int k) { return geom_here(k); }
+
+hipError_t VKT_MFMA_FN(launch_filter_mfma)(const FilterJob& j, bool six_products, hipStream_t s)
 {
     switch (j.fmt) {
-    case vktDataFormatUInt8: return dispatch_k<uint8_t, kU8>(j, j.wscale, s);
-    case vktDataFormatUInt16: return dispatch_k<uint16_t, kU16>(j, j.wscale, s);
+    case vktDataFormatUInt8: return dispatch_k<uint8_t, kU8>(j, s);
+    case vktDataFormatUInt16: return dispatch_k<uint16_t, kU16>(j, s);
     case vktDataFormatFloat32:
-        return six_products ? dispatch_k<float, kF32x6>(j, 1.0f, s)
-                            : dispatch_k<float, kF32x3>(j, 1.0f, s);
+        return six_products ? dispatch_k<float, kF32x6>(j, s) : dispatch_k<float, kF32x3>(j, s);
     }
     return hipErrorInvalidValue;
+}
+
+const void* VKT_MFMA_FN(mfma_batched_kernel)(vktDataFormat f, int k, bool six_products)
+{
+    switch (f) {
+    case vktDataFormatUInt8: return batched_k<uint8_t, kU8>(k);
+    case vktDataFormatUInt16: return batched_k<uint16_t, kU16>(k);
+    case vktDataFormatFloat32:
+        return six_products ? batched_k<float, kF32x6>(k) : batched_k<float, kF32x3>(k);
+    }
+    return nullptr;
 }
 
 }  // namespace vkt

@@ -11,18 +11,20 @@
 //    through a z-slab of output planes.  Each input plane of the slab, with an
 //    r-wide halo in x and y, is gathered once (address mode applied to halo
 //    coordinates only, through per-thread 32-bit in-plane offsets computed once
-//    per workgroup) and staged in LDS as FP32 (or int32), double buffered; the
-//    next plane's loads are in flight while the current plane is computed.
+//    per tile) and staged in LDS as FP32 (or int32), double buffered; the next
+//    plane's loads are in flight while the current plane is computed.
 //  * Input-stationary z ring: a thread owns 4 (x) x 2 (y) output columns and
 //    keeps k partial sums per output, one for each output plane zi - c + r the
 //    current input plane zi feeds.  A plane is read from LDS once per thread
 //    (16-byte reads of its (4+k-1)-wide row windows) and feeds all k^3 taps.
 //    After the plane, the ring's oldest entry is a finished output: it is
 //    rounded, stored, and the ring advances.
-//  * Weights are uniform: they are read with scalar loads as the operand of
-//    each multiply-add, re-issued per row group so they are never spilled.
-//  * Workgroups are numbered XCD-aware so tiles adjacent in x/y at the same z
-//    share an XCD's L2 for their halo re-reads.
+//  * Weights are uniform: they are scalar operands of the multiply-adds,
+//    re-loaded per weight group so they are never hoisted and spilled.
+//  * Single-volume launches number workgroups XCD-aware so tiles adjacent in
+//    x/y at the same z share an XCD's L2 for their halo re-reads; batched
+//    launches run persistent workgroups that take tile-slabs of many volumes
+//    from a work queue.
 #include "vkt_internal.h"
 
 #include <type_traits>
@@ -44,27 +46,8 @@ struct Geo {
     static constexpr int WX = kVX + K - 1;                // row window per thread
     static constexpr int NR = (WX + 3) / 4;               // 16-byte reads per row
     static constexpr int NROW = kVY + K - 1;              // input rows per thread
+    static constexpr int LDS_CELLS = HY * P;              // one plane buffer
     static_assert(4 * (kBX - 1) + 4 * NR <= P, "row window exceeds LDS pitch");
-};
-
-struct ValuArgs {
-    int32_t X, Y, Z;
-    int32_t mode;         // vktAddressMode
-    int32_t tz;           // output planes per slab
-    int32_t tiles_x, tiles_y;
-    uint32_t nblocks;
-    int32_t epi;          // kEpi* below
-    int32_t D;            // integer filter divisor
-    UDiv div2D;           // magic constants for 2D
-    float inv_D;
-    int32_t vec_ok;       // X % 4 == 0 and dst 4-cell aligned
-};
-
-enum : int32_t {
-    kEpiFloat = 0,        // float32 cells, float weights: store T
-    kEpiFloatDiv = 1,     // float32 cells, integer weights: store T / D
-    kEpiRound = 2,        // integer cells, float weights: floor(T + 1/2), saturate
-    kEpiIntDiv = 3        // integer cells, integer weights: floor((2T + D) / 2D)
 };
 
 // Address mode on one axis; -1 means "outside, reads zero" (border).
@@ -136,7 +119,7 @@ __device__ inline uint32_t udiv(uint32_t n, UDiv d)
 
 // Stored value of one finished output.
 template <typename T, typename Acc>
-__device__ inline T finish(Acc acc, const ValuArgs& a)
+__device__ inline T finish(Acc acc, const VolDesc& a)
 {
     if constexpr (std::is_same<T, float>::value) {
         return a.epi == kEpiFloatDiv ? (float)acc * a.inv_D : (float)acc;
@@ -154,20 +137,18 @@ __device__ inline T finish(Acc acc, const ValuArgs& a)
     }
 }
 
-template <typename T, int K, bool IACC, bool BORDER>
-__global__ __launch_bounds__(kNT) void filter_valu_kernel(
-    const T* __restrict__ src, T* __restrict__ dst,
-    const typename AccT<IACC>::type* __restrict__ w, ValuArgs a)
+// One tile-slab: output tile `tile` of z-slab `slab` of volume a.
+template <typename T, int K, bool IACC>
+__device__ void valu_tile(const VolDesc& a, const typename AccT<IACC>::type* __restrict__ w,
+                          int tile, int slab, typename AccT<IACC>::type* lds)
 {
     using G = Geo<K>;
     using Acc = typename AccT<IACC>::type;
     constexpr int R = G::R;
-    __shared__ __align__(16) Acc lds[2][G::HY * G::P];
+    const T* __restrict__ src = static_cast<const T*>(a.src);
+    T* __restrict__ dst = static_cast<T*>(a.dst);
 
     const int t = threadIdx.x, tx = t % kBX, ty = t / kBX;
-    const uint32_t lid = xcd_remap(blockIdx.x, a.nblocks);
-    const uint32_t ntiles = (uint32_t)a.tiles_x * (uint32_t)a.tiles_y;
-    const int tile = (int)(lid % ntiles), slab = (int)(lid / ntiles);
     const int x0 = (tile % a.tiles_x) * kTX, y0 = (tile / a.tiles_x) * kTY;
     const int zb = slab * a.tz, ze = min(zb + a.tz, a.Z);
     const int64_t plane = (int64_t)a.X * a.Y;
@@ -214,7 +195,7 @@ __global__ __launch_bounds__(kNT) void filter_valu_kernel(
 
     const int zi_beg = zb - R, zi_end = ze + R;  // input planes [beg, end)
     gather(zi_beg);
-    put(lds[0]);
+    put(lds);
     __syncthreads();
 
     const int ox = x0 + kVX * tx, oy = y0 + kVY * ty;
@@ -225,7 +206,7 @@ __global__ __launch_bounds__(kNT) void filter_valu_kernel(
         // iteration re-reads a valid plane and discards it)
         gather(min(zi + 1, zi_end - 1));
 
-        const Acc* buf = lds[cur] + (kVY * ty) * G::P + kVX * tx;
+        const Acc* buf = lds + cur * G::LDS_CELLS + (kVY * ty) * G::P + kVX * tx;
         using V4 = typename std::conditional<IACC, int4, float4>::type;
         if constexpr (K <= 5) {
             // all (2 + k - 1) row windows in registers, then taps grouped by
@@ -291,7 +272,7 @@ __global__ __launch_bounds__(kNT) void filter_valu_kernel(
             }
         }
 
-        put(lds[cur ^ 1]);
+        put(lds + (cur ^ 1) * G::LDS_CELLS);
 
         // ---- the ring's oldest entry is output plane zo = zi - r
         const int zo = zi - R;
@@ -336,45 +317,67 @@ __global__ __launch_bounds__(kNT) void filter_valu_kernel(
 }
 
 template <typename T, int K, bool IACC>
+__global__ __launch_bounds__(kNT) void filter_valu_kernel(
+    VolDesc a, const typename AccT<IACC>::type* __restrict__ w, uint32_t nblocks)
+{
+    using Acc = typename AccT<IACC>::type;
+    __shared__ __align__(16) Acc lds[2 * Geo<K>::LDS_CELLS];
+    const uint32_t lid = xcd_remap(blockIdx.x, nblocks);
+    const uint32_t ntiles = (uint32_t)a.tiles_x * (uint32_t)a.tiles_y;
+    valu_tile<T, K, IACC>(a, w, (int)(lid % ntiles), (int)(lid / ntiles), lds);
+}
+
+// Persistent workgroups: take items (volume, tile-slab) from the queue until
+// it is empty; the last workgroup to finish resets the queue counters.
+template <typename T, int K, bool IACC>
+__global__ __launch_bounds__(kNT) void filter_valu_batched_kernel(BatchArgs b)
+{
+    using Acc = typename AccT<IACC>::type;
+    __shared__ __align__(16) Acc lds[2 * Geo<K>::LDS_CELLS];
+    __shared__ uint32_t s_item;
+    const Acc* pool;
+    if constexpr (IACC) pool = b.wipool; else pool = b.wpool;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(&b.counters[0], 1u);
+        __syncthreads();
+        const uint32_t it = s_item;
+        __syncthreads();
+        if (it >= b.nitems) break;
+        const WorkItem wi = b.items[it];
+        const VolDesc a = b.vols[wi.vol];
+        const uint32_t ntiles = (uint32_t)a.tiles_x * (uint32_t)a.tiles_y;
+        valu_tile<T, K, IACC>(a, pool + a.woff, (int)(wi.lid % ntiles), (int)(wi.lid / ntiles),
+                              lds);
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&b.counters[1], 1u) == gridDim.x - 1) {
+            atomicExch(&b.counters[0], 0u);
+            atomicExch(&b.counters[1], 0u);
+        }
+    }
+}
+
+template <typename T, int K, bool IACC>
 hipError_t launch_k(const FilterJob& j, hipStream_t s)
 {
-    ValuArgs a{};
-    a.X = j.X;
-    a.Y = j.Y;
-    a.Z = j.Z;
-    a.mode = j.mode;
-    a.tiles_x = (j.X + kTX - 1) / kTX;
-    a.tiles_y = (j.Y + kTY - 1) / kTY;
-    const int64_t ntiles = (int64_t)a.tiles_x * a.tiles_y;
+    const ClassGeom g = valu_geom(K);
+    const int64_t ntiles = (int64_t)((j.X + g.tx - 1) / g.tx) * ((j.Y + g.ty - 1) / g.ty);
     // z-slab depth: enough workgroups to fill 256 CUs several times over,
-    // slabs deep enough to amortise the 2r halo planes.
+    // slabs deep enough to amortise the 2r halo planes
     const int64_t want_slabs = (2048 + ntiles - 1) / ntiles;
     int tz = (int)((j.Z + want_slabs - 1) / want_slabs);
-    const int tz_min = 4 > 2 * K ? 4 : 2 * K;
-    if (tz < tz_min) tz = tz_min;
+    if (tz < g.tz_min) tz = g.tz_min;
     if (tz > 64) tz = 64;
     if (tz > j.Z) tz = j.Z;
-    a.tz = tz;
+    const VolDesc a = make_desc(j, tz, g);
     const int64_t nb = ntiles * ((j.Z + tz - 1) / tz);
     if (nb > 0x7fffffff) return hipErrorInvalidValue;
-    a.nblocks = (uint32_t)nb;
-    if (j.fmt == vktDataFormatFloat32) a.epi = j.int_filter ? kEpiFloatDiv : kEpiFloat;
-    else a.epi = j.int_filter ? kEpiIntDiv : kEpiRound;
-    a.D = j.D;
-    a.div2D = j.div2D;
-    a.inv_D = j.inv_D;
-    a.vec_ok = j.vec_store ? 1 : 0;
     using Acc = typename AccT<IACC>::type;
     const Acc* w;
     if constexpr (IACC) w = j.wi; else w = j.wf;
-    const T* src = static_cast<const T*>(j.src);
-    T* dst = static_cast<T*>(j.dst);
-    if (j.mode == vktAddressModeBorder)
-        hipLaunchKernelGGL((filter_valu_kernel<T, K, IACC, true>), dim3((unsigned)nb),
-                           dim3(kNT), 0, s, src, dst, w, a);
-    else
-        hipLaunchKernelGGL((filter_valu_kernel<T, K, IACC, false>), dim3((unsigned)nb),
-                           dim3(kNT), 0, s, src, dst, w, a);
+    hipLaunchKernelGGL((filter_valu_kernel<T, K, IACC>), dim3((unsigned)nb), dim3(kNT), 0, s,
+                       a, w, (uint32_t)nb);
     return hipGetLastError();
 }
 
@@ -394,7 +397,32 @@ hipError_t dispatch_k(const FilterJob& j, hipStream_t s)
     return hipErrorInvalidValue;
 }
 
+template <typename T, bool IACC>
+const void* batched_k(int k)
+{
+    switch (k) {
+    case 1: return (const void*)&filter_valu_batched_kernel<T, 1, IACC>;
+    case 3: return (const void*)&filter_valu_batched_kernel<T, 3, IACC>;
+    case 5: return (const void*)&filter_valu_batched_kernel<T, 5, IACC>;
+    case 7: return (const void*)&filter_valu_batched_kernel<T, 7, IACC>;
+    case 9: return (const void*)&filter_valu_batched_kernel<T, 9, IACC>;
+    case 11: return (const void*)&filter_valu_batched_kernel<T, 11, IACC>;
+    case 13: return (const void*)&filter_valu_batched_kernel<T, 13, IACC>;
+    case 15: return (const void*)&filter_valu_batched_kernel<T, 15, IACC>;
+    }
+    return nullptr;
+}
+
 }  // namespace
+
+ClassGeom valu_geom(int k)
+{
+    ClassGeom g;
+    g.tx = kTX;
+    g.ty = kTY;
+    g.tz_min = 4 > 2 * k ? 4 : 2 * k;
+    return g;
+}
 
 hipError_t launch_filter_valu(const FilterJob& j, hipStream_t s)
 {
@@ -407,6 +435,19 @@ hipError_t launch_filter_valu(const FilterJob& j, hipStream_t s)
         return dispatch_k<float, false>(j, s);
     }
     return hipErrorInvalidValue;
+}
+
+const void* valu_batched_kernel(vktDataFormat f, int k, bool int_acc)
+{
+    switch (f) {
+    case vktDataFormatUInt8:
+        return int_acc ? batched_k<uint8_t, true>(k) : batched_k<uint8_t, false>(k);
+    case vktDataFormatUInt16:
+        return int_acc ? batched_k<uint16_t, true>(k) : batched_k<uint16_t, false>(k);
+    case vktDataFormatFloat32:
+        return int_acc ? nullptr : batched_k<float, false>(k);
+    }
+    return nullptr;
 }
 
 }  // namespace vkt

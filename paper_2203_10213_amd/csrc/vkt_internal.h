@@ -9,6 +9,30 @@
 
 #include "../../include/vkt.h"
 
+// Handle types of the C interface.
+struct vktStructuredVolume_ {
+    int32_t dims[3];
+    vktDataFormat fmt;
+    float cell[3];
+    float lo, hi;
+    void* dev;
+    bool owned;
+    int device;
+};
+
+struct vktFilter_ {
+    int32_t k;
+    bool is_int;
+    int32_t divisor;
+    int64_t sum_abs_int;        // sum |w| for integer filters
+    float wscale;               // power of two: max|w| * wscale in [2^14, 2^15)
+    uint64_t serial;            // unique per created filter (plan cache keys)
+    float* d_wf;                // device float weights (k^3)
+    int32_t* d_wi;              // device int weights (k^3), integer filters
+    int device;
+};
+
+
 namespace vkt {
 
 // Number of bytes of one cell of a format.
@@ -47,6 +71,57 @@ struct FilterJob {
     float wscale;            // 2^s with max|w| * 2^s in [2^14, 2^15) (fp16 splitting)
 };
 
+// Stored-result rule of an ApplyFilter.
+enum : int32_t {
+    kEpiFloat = 0,        // float32 cells, float weights: store T
+    kEpiFloatDiv = 1,     // float32 cells, integer weights: store T / D
+    kEpiRound = 2,        // integer cells, float weights: floor(T + 1/2), saturate
+    kEpiIntDiv = 3        // integer cells, integer weights: floor((2T + D) / 2D)
+};
+
+// Per-volume descriptor shared by the single-volume launches (passed by value)
+// and the batched persistent kernels (an array in device memory).  Weights are
+// addressed as pool + woff so that they stay scalar loads from a kernel
+// argument.
+struct VolDesc {
+    const void* src;
+    void* dst;
+    int32_t X, Y, Z;
+    int32_t mode;
+    int32_t tz;              // output planes per z-slab
+    int32_t tiles_x, tiles_y;
+    uint32_t woff;           // first weight of this volume's filter in the pool
+    int32_t epi;             // stored-result rule (kEpi*)
+    int32_t D;
+    UDiv div2D;
+    float inv_D;
+    int32_t vec_ok;
+    float wscale, unscale;   // fp16 weight scaling of the matrix-core path
+};
+
+// One work item of a batched launch: a tile-slab of one volume.
+struct WorkItem {
+    uint32_t vol;
+    uint32_t lid;            // slab * tiles_x * tiles_y + tile
+};
+
+// Arguments of a batched persistent kernel (one arithmetic class).
+struct BatchArgs {
+    const VolDesc* vols;
+    const WorkItem* items;   // sorted longest first
+    uint32_t nitems;
+    uint32_t* counters;      // [0] next item, [1] finished workgroups; both
+                             // return to 0 when the launch ends
+    const float* wpool;      // float weights of all filters of the class
+    const int32_t* wipool;   // int weights (integer accumulation class)
+};
+
+// Tile geometry of a kernel class (for planning).
+struct ClassGeom {
+    int tx, ty;              // output tile in x and y
+    int tz_min;              // smallest useful slab depth
+};
+
 // Kernel launchers (return the launch status).
 hipError_t launch_fill(void* dst, int cell_bytes, int64_t n_cells,
                        uint32_t raw_bits, hipStream_t s);
@@ -57,5 +132,36 @@ hipError_t launch_filter_valu(const FilterJob& j, hipStream_t s);
 // Matrix-core path for float-weight filters with k >= 5.  six_products
 // selects the 6-product bf16 split for float32 volumes (else 3 products).
 hipError_t launch_filter_mfma(const FilterJob& j, bool six_products, hipStream_t s);
+
+// The matrix-core kernels are built twice: 16x16x32 tiles for k <= 7 (_s16)
+// and 32x32x16 tiles for k >= 9 (_s32); the unsuffixed functions dispatch.
+hipError_t launch_filter_mfma_s16(const FilterJob& j, bool six_products, hipStream_t s);
+hipError_t launch_filter_mfma_s32(const FilterJob& j, bool six_products, hipStream_t s);
+const void* mfma_batched_kernel_s16(vktDataFormat f, int k, bool six_products);
+const void* mfma_batched_kernel_s32(vktDataFormat f, int k, bool six_products);
+ClassGeom mfma_geom_s16(int k);
+ClassGeom mfma_geom_s32(int k);
+
+// Batched persistent kernels: the kernel function of a class (for launches
+// and graph kernel nodes, taking one BatchArgs by value), its geometry, and
+// the workgroup count that fills the device once.
+const void* valu_batched_kernel(vktDataFormat f, int k, bool int_acc);
+ClassGeom valu_geom(int k);
+const void* mfma_batched_kernel(vktDataFormat f, int k, bool six_products);
+ClassGeom mfma_geom(int k);
+// Fill in the descriptor fields the kernels derive from a FilterJob.
+VolDesc make_desc(const FilterJob& j, int tz, ClassGeom g);
+
+// Validation and planning shared by the single and batched calls: fills j
+// and the chosen path (mfma, six products) for one (dst, src, filter) triple.
+vktError build_job(const vktStructuredVolume_* dst, const vktStructuredVolume_* src,
+                   const vktFilter_* filt, int mode, vktPrecision prec, FilterJob& j,
+                   bool& mfma, bool& six);
+bool live_volume(const vktStructuredVolume_* v);
+bool live_filter(const vktFilter_* f);
+vktError from_hip(hipError_t e);
+hipStream_t thread_stream();
+vktPrecision thread_precision();
+bool thread_autotune();
 
 }  // namespace vkt

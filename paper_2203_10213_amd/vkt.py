@@ -47,6 +47,8 @@ SIGNATURES = {
     "vktFillSV": [_P, _F],
     "vktFillRangeSV": [_P, _I32, _I32, _I32, _I32, _I32, _I32, _F],
     "vktApplyFilter": [_P, _P, _P, ctypes.c_int],
+    "vktApplyFilterBatched": [_I32, _PP, _PP, _PP, ctypes.c_int],
+    "vktSetAutotune": [ctypes.c_int],
     "vktSetStream": [_P],
     "vktGetStream": [_PP],
     "vktSetPrecision": [ctypes.c_int],
@@ -193,6 +195,17 @@ def vktApplyFilter(dst, src, filt, mode=vktAddressModeClamp):
     _ok(lib().vktApplyFilter(dst, src, filt, m), "vktApplyFilter")
 
 
+def vktApplyFilterBatched(dsts, srcs, filts, mode=vktAddressModeClamp):
+    """dsts, srcs, filts: equal-length sequences of handles."""
+    n = len(dsts)
+    if len(srcs) != n or len(filts) != n:
+        raise ValueError("batched call needs equal-length handle lists")
+    arr = ctypes.c_void_p * max(n, 1)
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    _ok(lib().vktApplyFilterBatched(n, arr(*dsts), arr(*srcs), arr(*filts), m),
+        "vktApplyFilterBatched")
+
+
 # ------------------------------------------------------------- thread state --
 
 def vktSetStream(stream):
@@ -217,6 +230,10 @@ def vktGetPrecision():
     p = ctypes.c_int()
     _ok(lib().vktGetPrecision(ctypes.byref(p)), "vktGetPrecision")
     return p.value
+
+
+def vktSetAutotune(enable):
+    _ok(lib().vktSetAutotune(1 if enable else 0), "vktSetAutotune")
 
 
 def vktSynchronize():

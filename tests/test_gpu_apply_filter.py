@@ -37,9 +37,12 @@ def _fresh_precision():
 SHAPES = [(1, 1, 1), (3, 2, 1), (5, 1, 70), (9, 33, 65), (20, 40, 130), (7, 70, 3)]
 
 
+@pytest.mark.parametrize("precision", ["fp32", "auto"])
 @pytest.mark.parametrize("dtype", [np.uint8, np.uint16, np.float32])
 @pytest.mark.parametrize("mode", MODES)
-def test_float_weights_sweep(orc, dtype, mode):
+def test_float_weights_sweep(orc, dtype, mode, precision):
+    """fp32 runs every k on the vector ALUs; auto sends k >= 5 to the
+    matrix cores (6-product split for float32)."""
     g = np.random.default_rng(100 + MODES.index(mode))
     for shape in SHAPES:
         for k in KS:
@@ -49,7 +52,7 @@ def test_float_weights_sweep(orc, dtype, mode):
             w = g.standard_normal((k, k, k)).astype(np.float32)
             if dtype != np.float32:
                 w = np.abs(w) / np.abs(w).sum()  # keep integer results in range
-            out = run_filter(src, w, mode)
+            out = run_filter(src, w, mode, precision=precision)
             check_against_oracle(orc, src, w, mode, out, what=f"{shape} k={k}")
 
 
@@ -75,14 +78,15 @@ def test_integer_weights_on_float_volume(orc):
     check_against_oracle(orc, src, w, "mirror", out, divisor=9)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "auto"])
 @pytest.mark.parametrize("dtype", [np.uint8, np.uint16, np.float32])
-def test_delta_is_identity_bit_exact(dtype):
+def test_delta_is_identity_bit_exact(dtype, precision):
     g = np.random.default_rng(3)
     src = _vol(g, (11, 37, 71), dtype)
     for k, mode in itertools.product((1, 3, 7, 15), MODES):
         w = np.zeros((k, k, k), np.float32)
         w[k // 2, k // 2, k // 2] = 1.0
-        assert np.array_equal(run_filter(src, w, mode), src), (k, mode)
+        assert np.array_equal(run_filter(src, w, mode, precision=precision), src), (k, mode)
 
 
 def test_off_centre_delta_orientation():
