@@ -83,26 +83,35 @@ def make_cases(name, device):
     return cases
 
 
-def kernel_source_sha():
-    """Hash of the HIP sources; profile-derived traffic is only reported for
-    the kernels it was measured on."""
+KERNEL_SOURCES = {
+    "valu": ["vkt_filter_valu.hip", "vkt_internal.h"],
+    "dot4": ["vkt_filter_dot4.hip", "vkt_internal.h"],
+    "mfma": ["vkt_filter_mfma.hip", "vkt_internal.h"],
+}
+
+
+def kernel_source_sha(path):
+    """Hash of the HIP sources of one kernel path; profile-derived traffic is
+    only reported for the kernel it was measured on."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2203_10213_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in KERNEL_SOURCES[path]:
+        p = os.path.join(csrc, f)
+        if os.path.exists(p):
+            h.update(open(p, "rb").read())
     return h.hexdigest()[:16]
 
 
-def stored_traffic(case_name):
+def stored_traffic(case_name, path):
     """HBM bytes per launch from committed rocprofv3 --pmc summaries, scaled
-    by the copy-kernel calibration, if they match the current kernels."""
+    by the copy-kernel calibration, if they match the current kernel."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
     try:
         d = json.load(open(p))
         e = d.get(case_name)
-        if e and e.get("kernel_src_sha") == kernel_source_sha():
+        if e and e.get("path") == path and e.get("kernel_src_sha") == kernel_source_sha(path):
             return e["hbm_bytes_per_launch"]
     except (ValueError, KeyError):
         pass
@@ -275,7 +284,7 @@ def main():
     d = per_case[dom]
     roof = dict(d["roofline"])
     roof["kernel_case"] = d["case"]
-    roof["traffic"] = stored_traffic(d["case"])
+    roof["traffic"] = stored_traffic(d["case"], d["path"])
 
     cpu = None
     if not args.no_cpu_baseline:
