@@ -126,16 +126,49 @@ vktError create_filter(vktFilter* out, int32_t k, const float* wf, const int32_t
     if (hipGetDevice(&device) != hipSuccess) return vktDeviceError;
     float* dwf = nullptr;
     int32_t* dwi = nullptr;
-    hipError_t e = hipMalloc(&dwf, n * sizeof(float));
-    if (e == hipSuccess) e = hipMemcpy(dwf, hf.data(), n * sizeof(float), hipMemcpyHostToDevice);
+    // zero-padded copies (wide scalar loads of the last weight group)
+    const size_t npad = (size_t)n + vkt::kWeightPad;
+    hf.resize(npad, 0.f);
+    hipError_t e = hipMalloc(&dwf, npad * sizeof(float));
+    if (e == hipSuccess) e = hipMemcpy(dwf, hf.data(), npad * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess && wi) {
-        e = hipMalloc(&dwi, n * sizeof(int32_t));
+        hi.resize(npad, 0);
+        e = hipMalloc(&dwi, npad * sizeof(int32_t));
         if (e == hipSuccess)
-            e = hipMemcpy(dwi, hi.data(), n * sizeof(int32_t), hipMemcpyHostToDevice);
+            e = hipMemcpy(dwi, hi.data(), npad * sizeof(int32_t), hipMemcpyHostToDevice);
+    }
+    // 8-bit packed rows for the dot-product path (uint8 volumes): weights all
+    // in [0, 255] (unsigned) or all in [-128, 127] (signed), k <= 7, and
+    // sum|w| and D small enough for its exact FP32 epilogue
+    uint32_t* dwq = nullptr;
+    bool q_ok = false, q_signed = false;
+    int64_t sum_int = 0;
+    if (wi) {
+        bool u8 = true, s8 = true;
+        for (int i = 0; i < n; ++i) {
+            u8 = u8 && hi[i] >= 0 && hi[i] <= 255;
+            s8 = s8 && hi[i] >= -128 && hi[i] <= 127;
+            sum_int += hi[i];
+        }
+        q_ok = (k == 3 || k == 5 || k == 7) && (u8 || s8) && sum_abs <= 2048 &&
+               divisor <= (1 << 19);
+        q_signed = !u8;
+    }
+    if (e == hipSuccess && q_ok) {
+        const int nh = (k + 3) / 4, nw = vkt::dot4_words(k);
+        std::vector<uint32_t> hq((size_t)nw + vkt::kWeightPad, 0u);
+        for (int row = 0; row < k * k; ++row)
+            for (int a = 0; a < k; ++a)
+                hq[(size_t)row * nh + a / 4] |= ((uint32_t)hi[(size_t)row * k + a] & 0xffu)
+                                                << (8 * (a % 4));
+        e = hipMalloc(&dwq, hq.size() * sizeof(uint32_t));
+        if (e == hipSuccess)
+            e = hipMemcpy(dwq, hq.data(), hq.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
     }
     if (e != hipSuccess) {
         if (dwf) (void)hipFree(dwf);
         if (dwi) (void)hipFree(dwi);
+        if (dwq) (void)hipFree(dwq);
         return from_hip(e);
     }
     // power-of-two weight scale for fp16 operand splitting
@@ -148,10 +181,12 @@ vktError create_filter(vktFilter* out, int32_t k, const float* wf, const int32_t
         wscale = std::ldexp(1.f, 15 - ex);     // amax * wscale in [2^14, 2^15)
     }
     auto* f = new (std::nothrow) vktFilter_{k, wi != nullptr, wi ? divisor : 1, sum_abs,
-                                            wscale, 0, dwf, dwi, device};
+                                            wscale, 0, dwf, dwi, dwq, q_ok, q_signed,
+                                            sum_int, device};
     if (!f) {
         (void)hipFree(dwf);
         if (dwi) (void)hipFree(dwi);
+        if (dwq) (void)hipFree(dwq);
         return vktOutOfMemory;
     }
     {
@@ -211,6 +246,7 @@ VolDesc make_desc(const FilterJob& j, int tz, ClassGeom g)
     a.vec_ok = j.vec_store ? 1 : 0;
     a.wscale = j.fmt == vktDataFormatFloat32 ? 1.0f : j.wscale;  // bf16 pieces are unscaled
     a.unscale = 1.0f / a.wscale;
+    a.bias = j.q_bias;
     return a;
 }
 
@@ -259,8 +295,20 @@ vktError build_job(const vktStructuredVolume_* dst, const vktStructuredVolume_* 
     j.wscale = filt->wscale;
     // Plan: float-weight filters with k >= 5 run on the matrix cores unless
     // the precision is FP32; everything else (k < 5, integer weights, whose
-    // results are exact integers) runs on the vector ALUs.
+    // results are exact integers) runs on the vector ALUs, uint8 volumes with
+    // small integer weights as 8-bit dot products (4-byte rows and buffers).
     mfma = !filt->is_int && filt->k >= 5 && prec != vktPrecisionFP32;
+    j.dot4 = filt->q_ok && src->fmt == vktDataFormatUInt8 && j.X % 4 == 0 &&
+             reinterpret_cast<uintptr_t>(src->dev) % 4 == 0 &&
+             reinterpret_cast<uintptr_t>(dst->dev) % 4 == 0;
+    j.q_signed = filt->q_signed;
+    j.wq = filt->d_wq;
+    if (j.dot4) {
+        // floor(T/D + 1/2) as floor(T * (1/D) + bias); signed weights add the
+        // 128 * sum(w) the cells lost by entering as s - 128
+        const double D = (double)filt->divisor;
+        j.q_bias = (float)(0.5 + 0.25 / D + (filt->q_signed ? 128.0 * (double)filt->sum_int / D : 0.0));
+    }
     // float32 cells: the 6-product split keeps every product term down to
     // 2^-16 relative (about 1e-7 after rounding); Auto uses it.  The 3-product
     // split drops three terms of up to 2^-16 each and is opt-in.
@@ -374,8 +422,9 @@ vktError vktFilterDestroy(vktFilter f)
         if (!f || !g_filters.erase(f)) return vktInvalidValue;
     }
     hipError_t e = hipFree(f->d_wf);
-    if (f->d_wi) {
-        hipError_t e2 = hipFree(f->d_wi);
+    for (void* p : {(void*)f->d_wi, (void*)f->d_wq}) {
+        if (!p) continue;
+        hipError_t e2 = hipFree(p);
         if (e == hipSuccess) e = e2;
     }
     delete f;
@@ -417,6 +466,7 @@ vktError vktApplyFilter(vktStructuredVolume dst, vktStructuredVolume src, vktFil
     const vktError e = vkt::build_job(dst, src, filt, mode, state().precision, j, mfma, six);
     if (e != vktNoError) return e;
     if (mfma) return from_hip(vkt::launch_filter_mfma(j, six, state().stream));
+    if (j.dot4) return from_hip(vkt::launch_filter_dot4(j, state().stream));
     return from_hip(vkt::launch_filter_valu(j, state().stream));
 }
 

@@ -32,7 +32,9 @@ namespace vkt {
 namespace {
 
 struct ClassKey {
-    int fmt, k, path, flag;  // path 0 = vector ALU (flag: int accumulate), 1 = matrix (flag: 6 products)
+    // path 0 = vector ALU (flag: int accumulate), 1 = matrix (flag: 6
+    // products), 2 = 8-bit dot products (flag: signed weights)
+    int fmt, k, path, flag;
     bool operator<(const ClassKey& o) const
     {
         return std::tie(fmt, k, path, flag) < std::tie(o.fmt, o.k, o.path, o.flag);
@@ -41,11 +43,20 @@ struct ClassKey {
 
 const void* class_kernel(const ClassKey& c)
 {
+    if (c.path == 2) return dot4_batched_kernel(c.k, c.flag != 0);
     return c.path ? mfma_batched_kernel((vktDataFormat)c.fmt, c.k, c.flag != 0)
                   : valu_batched_kernel((vktDataFormat)c.fmt, c.k, c.flag != 0);
 }
 
-ClassGeom class_geom(const ClassKey& c) { return c.path ? mfma_geom(c.k) : valu_geom(c.k); }
+ClassGeom class_geom(const ClassKey& c)
+{
+    if (c.path == 2) return dot4_geom(c.k);
+    return c.path ? mfma_geom(c.k) : valu_geom(c.k);
+}
+
+// Weights per filter in the class's pools: k^3 (float and int pools), or the
+// packed 8-bit rows (int pool) of the dot-product path.
+int class_weights(const ClassKey& c) { return c.path == 2 ? dot4_words(c.k) : c.k * c.k * c.k; }
 
 // ---- tuning table: (class, size class) -> z-slab depth ---------------------
 
@@ -187,7 +198,7 @@ void class_arrays(const std::vector<Triple>& tr, ClassPlan& cp, std::vector<VolD
     wf.clear();
     wi.clear();
     std::map<uint64_t, uint32_t> woff;  // filter serial -> pool offset
-    const int n3 = cp.key.k * cp.key.k * cp.key.k;
+    const int n3 = class_weights(cp.key);
     for (int idx : cp.members) {
         const Triple& t = tr[idx];
         VolDesc a = make_desc(t.j, std::min(cp.tz, t.j.Z), g);
@@ -214,10 +225,15 @@ hipError_t upload_class(const std::vector<Triple>& tr, ClassPlan& cp, char* base
     if (e == hipSuccess)
         e = hipMemcpy(base + cp.off_items, items.data(), items.size() * sizeof(WorkItem),
                       hipMemcpyHostToDevice);
-    const int n3 = cp.key.k * cp.key.k * cp.key.k;
+    const int n3 = class_weights(cp.key);
     for (size_t m = 0; m < cp.members.size() && e == hipSuccess; ++m) {
         const vktFilter_* f = tr[cp.members[m]].f;
         const uint32_t off = descs[m].woff;
+        if (cp.key.path == 2) {
+            e = hipMemcpy(base + cp.off_wi + off * sizeof(int32_t), f->d_wq,
+                          n3 * sizeof(uint32_t), hipMemcpyDeviceToDevice);
+            continue;
+        }
         e = hipMemcpy(base + cp.off_wf + off * sizeof(float), f->d_wf, n3 * sizeof(float),
                       hipMemcpyDeviceToDevice);
         if (e == hipSuccess && f->d_wi)
@@ -300,7 +316,7 @@ vktError build_plan(const std::vector<Triple>& tr, std::vector<uintptr_t>&& sig,
             nitems += (size_t)((j.X + geom.tx - 1) / geom.tx) * ((j.Y + geom.ty - 1) / geom.ty) *
                       ((j.Z + tzmin - 1) / tzmin);
         }
-        const size_t n3 = (size_t)cp.key.k * cp.key.k * cp.key.k;
+        const size_t n3 = (size_t)class_weights(cp.key);
         cp.off_desc = bytes = align_up(bytes, 256);
         bytes += cp.members.size() * sizeof(VolDesc);
         cp.off_items = bytes = align_up(bytes, 256);
@@ -308,9 +324,9 @@ vktError build_plan(const std::vector<Triple>& tr, std::vector<uintptr_t>&& sig,
         cp.off_cnt = bytes = align_up(bytes, 256);
         bytes += 2 * sizeof(uint32_t);
         cp.off_wf = bytes = align_up(bytes, 256);
-        bytes += cp.members.size() * n3 * sizeof(float);
+        bytes += (cp.members.size() * n3 + kWeightPad) * sizeof(float);
         cp.off_wi = bytes = align_up(bytes, 256);
-        bytes += cp.members.size() * n3 * sizeof(int32_t);
+        bytes += (cp.members.size() * n3 + kWeightPad) * sizeof(int32_t);
         int per_cu = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, cp.func, 256, 0) !=
                 hipSuccess ||
@@ -419,7 +435,9 @@ vktError vktApplyFilterBatched(int32_t n, const vktStructuredVolume* dst,
         if (e != vktNoError) return e;
         const FilterJob& j = tr[i].j;
         tr[i].f = filters[i];
-        tr[i].key = ClassKey{(int)j.fmt, j.k, mfma ? 1 : 0, mfma ? (six ? 1 : 0) : (j.int_acc ? 1 : 0)};
+        if (mfma) tr[i].key = ClassKey{(int)j.fmt, j.k, 1, six ? 1 : 0};
+        else if (j.dot4) tr[i].key = ClassKey{(int)j.fmt, j.k, 2, j.q_signed ? 1 : 0};
+        else tr[i].key = ClassKey{(int)j.fmt, j.k, 0, j.int_acc ? 1 : 0};
         sig.push_back((uintptr_t)j.src);
         sig.push_back((uintptr_t)j.dst);
         sig.push_back((uintptr_t)filters[i]->serial);

@@ -20,7 +20,9 @@
 //    After the plane, the ring's oldest entry is a finished output: it is
 //    rounded, stored, and the ring advances.
 //  * Weights are uniform: they are scalar operands of the multiply-adds,
-//    re-loaded per weight group so they are never hoisted and spilled.
+//    loaded one group (a filter plane for k = 3, else a filter row) at a
+//    time with explicit scalar loads.  For k >= 5 the row windows stream
+//    through registers one input row at a time.
 //  * Single-volume launches number workgroups XCD-aware so tiles adjacent in
 //    x/y at the same z share an XCD's L2 for their halo re-reads; batched
 //    launches run persistent workgroups that take tile-slabs of many volumes
@@ -76,14 +78,37 @@ __device__ inline uint32_t xcd_remap(uint32_t b, uint32_t n)
     return xcd < rem ? xcd * (q + 1) + idx : rem * (q + 1) + (xcd - rem) * q + idx;
 }
 
-// An SGPR value the compiler cannot see through: adding it to a uniform index
-// keeps loads inside the loop iteration that uses them.
-__device__ inline int opaque_zero()
+// Weight rows are read with explicit scalar loads that wait for their data
+// in the same statement.  The volatile statements keep their program order,
+// so one weight group at a time is live in SGPRs: the loads are neither
+// hoisted out of the z loop nor all issued at its top (which would spill
+// SGPRs into VGPR lanes).  A load of N dwords may read up to N - 1 dwords
+// past the last weight; weight buffers carry kWeightPad dwords of padding.
+template <int N> struct SRow;
+template <> struct SRow<4> { typedef uint32_t type __attribute__((ext_vector_type(4))); };
+template <> struct SRow<8> { typedef uint32_t type __attribute__((ext_vector_type(8))); };
+template <> struct SRow<16> { typedef uint32_t type __attribute__((ext_vector_type(16))); };
+
+template <int N, typename Acc>
+__device__ inline void load_weights(const Acc* p, Acc (&wv)[N])
 {
-    int z = 0;
-    asm volatile("" : "+s"(z));
-    return z;
+    typename SRow<N>::type r;
+    if constexpr (N == 4)
+        asm volatile("s_load_dwordx4 %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=&s"(r) : "s"(p));
+    else if constexpr (N == 8)
+        asm volatile("s_load_dwordx8 %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=&s"(r) : "s"(p));
+    else
+        asm volatile("s_load_dwordx16 %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=&s"(r) : "s"(p));
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        const uint32_t u = r[q];
+        if constexpr (std::is_same<Acc, float>::value) wv[q] = __uint_as_float(u);
+        else wv[q] = (Acc)u;
+    }
 }
+
+// Dwords of a scalar load covering n weights.
+constexpr int sload_width(int n) { return n <= 4 ? 4 : n <= 8 ? 8 : 16; }
 
 // Raw buffer loads: SGPR resource (base, size) + 32-bit VGPR byte offset.
 // An offset at or beyond the resource size reads 0 (used for border cells).
@@ -208,10 +233,9 @@ __device__ void valu_tile(const VolDesc& a, const typename AccT<IACC>::type* __r
 
         const Acc* buf = lds + cur * G::LDS_CELLS + (kVY * ty) * G::P + kVX * tx;
         using V4 = typename std::conditional<IACC, int4, float4>::type;
-        if constexpr (K <= 5) {
-            // all (2 + k - 1) row windows in registers, then taps grouped by
-            // filter plane c (k = 3) or filter row (c, b) (k = 5), so that at
-            // most 9 scalar weights are live per group
+        if constexpr (K <= 3) {
+            // all (2 + k - 1) row windows in registers, then the taps of one
+            // filter plane c at a time
             Acc v[G::NROW][G::NR * 4];
 #pragma unroll
             for (int jr = 0; jr < G::NROW; ++jr)
@@ -225,23 +249,22 @@ __device__ void valu_tile(const VolDesc& a, const typename AccT<IACC>::type* __r
                 }
 #pragma unroll
             for (int c = 0; c < K; ++c) {
-                const int oc = K <= 3 ? opaque_zero() : 0;
+                constexpr int NW = sload_width(K * K);
+                Acc wv[NW];
+                load_weights<NW>(w + c * K * K, wv);
 #pragma unroll
-                for (int b = 0; b < K; ++b) {
-                    const Acc* wp = w + (K <= 3 ? oc : opaque_zero()) + (c * K + b) * K;
+                for (int b = 0; b < K; ++b)
 #pragma unroll
-                    for (int aa = 0; aa < K; ++aa) {
-                        const Acc wv = wp[aa];
+                    for (int aa = 0; aa < K; ++aa)
 #pragma unroll
                         for (int vy = 0; vy < kVY; ++vy)
 #pragma unroll
                             for (int vx = 0; vx < kVX; ++vx)
-                                acc[c][vy][vx] = mac(wv, v[b + vy][vx + aa], acc[c][vy][vx]);
-                    }
-                }
+                                acc[c][vy][vx] = mac(wv[b * K + aa], v[b + vy][vx + aa],
+                                                     acc[c][vy][vx]);
             }
         } else {
-            // stream the row windows; k scalar weights live per (row, vy, c)
+            // stream the row windows; one filter row live per (row, vy, c)
 #pragma unroll 1
             for (int jr = 0; jr < G::NROW; ++jr) {
                 Acc v[G::NR * 4];
@@ -259,14 +282,14 @@ __device__ void valu_tile(const VolDesc& a, const typename AccT<IACC>::type* __r
                     if (b < 0 || b >= K) continue;
 #pragma unroll
                     for (int c = 0; c < K; ++c) {
-                        const Acc* wp = w + opaque_zero() + (c * K + b) * K;
+                        constexpr int NW = sload_width(K);
+                        Acc wv[NW];
+                        load_weights<NW>(w + (c * K + b) * K, wv);
 #pragma unroll
-                        for (int aa = 0; aa < K; ++aa) {
-                            const Acc wv = wp[aa];
+                        for (int aa = 0; aa < K; ++aa)
 #pragma unroll
                             for (int vx = 0; vx < kVX; ++vx)
-                                acc[c][vy][vx] = mac(wv, v[vx + aa], acc[c][vy][vx]);
-                        }
+                                acc[c][vy][vx] = mac(wv[aa], v[vx + aa], acc[c][vy][vx]);
                     }
                 }
             }

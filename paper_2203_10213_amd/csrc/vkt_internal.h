@@ -29,6 +29,11 @@ struct vktFilter_ {
     uint64_t serial;            // unique per created filter (plan cache keys)
     float* d_wf;                // device float weights (k^3)
     int32_t* d_wi;              // device int weights (k^3), integer filters
+    // 8-bit packed copy for the dot-product path (integer filters, k <= 7,
+    // weights in [0, 255] or [-128, 127]): k^2 rows of ceil(k/4) dwords
+    uint32_t* d_wq;
+    bool q_ok, q_signed;
+    int64_t sum_int;            // sum w for integer filters
     int device;
 };
 
@@ -52,6 +57,11 @@ struct UDiv {
 };
 UDiv make_udiv(uint32_t d);
 
+// Device weight buffers (per filter, and the batched pools) end with this
+// many zero dwords, so that a wide scalar load of the last weight group stays
+// inside the allocation.
+constexpr int kWeightPad = 16;
+
 // Everything one single-volume ApplyFilter launch needs.
 struct FilterJob {
     const void* src;
@@ -69,6 +79,10 @@ struct FilterJob {
     float inv_D;             // 1/D for float outputs of integer filters
     bool vec_store;          // dst rows can take 16-B-aligned vector stores
     float wscale;            // 2^s with max|w| * 2^s in [2^14, 2^15) (fp16 splitting)
+    bool dot4;               // uint8 cells, 8-bit packed integer weights
+    bool q_signed;           // signed 8-bit weights (cells enter as s - 128)
+    const uint32_t* wq;      // device packed weights
+    float q_bias;            // epilogue constant of the dot-product path
 };
 
 // Stored-result rule of an ApplyFilter.
@@ -97,6 +111,7 @@ struct VolDesc {
     float inv_D;
     int32_t vec_ok;
     float wscale, unscale;   // fp16 weight scaling of the matrix-core path
+    float bias;              // dot-product path: 1/2 + 1/(4D) (+ 128 sum(w) / D)
 };
 
 // One work item of a batched launch: a tile-slab of one volume.
@@ -129,6 +144,12 @@ hipError_t launch_fill_range(void* dst, int cell_bytes, int32_t X, int32_t Y,
                              const int32_t first[3], const int32_t last[3],
                              uint32_t raw_bits, hipStream_t s);
 hipError_t launch_filter_valu(const FilterJob& j, hipStream_t s);
+// 8-bit dot-product path for uint8 volumes with small integer filters.
+hipError_t launch_filter_dot4(const FilterJob& j, hipStream_t s);
+const void* dot4_batched_kernel(int k, bool q_signed);
+ClassGeom dot4_geom(int k);
+// Dwords of packed weights per filter on the dot-product path.
+inline int dot4_words(int k) { return k * k * ((k + 3) / 4); }
 // Matrix-core path for float-weight filters with k >= 5.  six_products
 // selects the 6-product bf16 split for float32 volumes (else 3 products).
 hipError_t launch_filter_mfma(const FilterJob& j, bool six_products, hipStream_t s);
