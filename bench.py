@@ -25,6 +25,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP32_VECTOR_PEAK_TF = 157.3    # MI355X FP32 vector (packed FMA), TFLOP/s
 BF16_MFMA_PEAK_TF = 2500.0     # MI355X dense bf16 matrix, TFLOP/s
+# 8-bit dot products on the vector ALUs: 256 CUs x 4 SIMDs x 16 lanes x 4 MACs
+# x 2 ops x 2.4 GHz (v_dot4 issues at the full VALU rate)
+INT8_DOT_PEAK_TOPS = 256 * 4 * 16 * 4 * 2 * 2.4e9 / 1e12
 
 
 def parse():
@@ -124,6 +127,8 @@ def arith_dtype(c, precision):
         if c["src"].dtype.is_floating_point:
             return "bf16x3->f32" if precision == "splitbf16" else "bf16x6->f32"
         return "f16x2->f32"
+    if c["path"] == "dot4":
+        return "u8dot4->i32"
     if c["D"] is not None:
         return "f32(exact int)"
     return "f32"
@@ -131,8 +136,24 @@ def arith_dtype(c, precision):
 
 def kernel_path(c, precision):
     """The library's plan rule: float-weight filters with k >= 5 run on the
-    matrix cores unless the precision is fp32; the rest on the vector ALUs."""
-    return "mfma" if (c["D"] is None and c["k"] >= 5 and precision != "fp32") else "valu"
+    matrix cores unless the precision is fp32; uint8 volumes with integer
+    filters of k <= 7, weights all in [0, 255] or all in [-128, 127],
+    sum |w| <= 2048, divisor <= 2^19 and rows of a multiple of 4 cells run as
+    8-bit dot products; the rest on the vector ALUs in FP32 / int32."""
+    import numpy as np
+    if c["D"] is None:
+        return "mfma" if (c["k"] >= 5 and precision != "fp32") else "valu"
+    w = np.asarray(c["w"], np.int64)
+    fits = (w.min() >= 0 and w.max() <= 255) or (w.min() >= -128 and w.max() <= 127)
+    if (c["src"].dtype == torch_uint8() and c["k"] in (3, 5, 7) and fits
+            and np.abs(w).sum() <= 2048 and c["D"] <= (1 << 19) and c["src"].shape[-1] % 4 == 0):
+        return "dot4"
+    return "valu"
+
+
+def torch_uint8():
+    import torch
+    return torch.uint8
 
 
 def case_roofline(c, ms):
@@ -145,13 +166,14 @@ def case_roofline(c, ms):
     flops = c["voxels"] * c["flops_per_voxel"]
     gbs = bytes_alg / t / 1e9
     tfs = flops / t / 1e12
-    peak_c = BF16_MFMA_PEAK_TF if c["path"] == "mfma" else FP32_VECTOR_PEAK_TF
+    peak_c = {"mfma": BF16_MFMA_PEAK_TF, "dot4": INT8_DOT_PEAK_TOPS}.get(c["path"], FP32_VECTOR_PEAK_TF)
     if bytes_alg / (HBM_PEAK_GBS * 1e9) >= flops / (peak_c * 1e12):
         roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": gbs / HBM_PEAK_GBS}
     else:
         roof = {"bound": "mfma" if c["path"] == "mfma" else "alu", "achieved": tfs,
-                "peak": peak_c, "unit": "TFLOP/s", "frac": tfs / peak_c}
+                "peak": peak_c, "unit": "TOP/s" if c["path"] == "dot4" else "TFLOP/s",
+                "frac": tfs / peak_c}
     return dict(case=c["name"], path=c["path"], ms=ms,
                 gvoxels_s=c["voxels"] / t / 1e9, hbm_gbs=gbs, hbm_frac=gbs / HBM_PEAK_GBS,
                 tflops=tfs, algorithmic_bytes=bytes_alg, flops=flops, roofline=roof)
