@@ -304,10 +304,10 @@ vktError build_job(const vktStructuredVolume_* dst, const vktStructuredVolume_* 
     j.q_signed = filt->q_signed;
     j.wq = filt->d_wq;
     if (j.dot4) {
-        // floor(T/D + 1/2) as floor(T * (1/D) + bias); signed weights add the
-        // 128 * sum(w) the cells lost by entering as s - 128
+        // floor(T/D + 1/2) as round-to-nearest(T * (1/D) + bias); signed
+        // weights add the 128 * sum(w) the cells lost by entering as s - 128
         const double D = (double)filt->divisor;
-        j.q_bias = (float)(0.5 + 0.25 / D + (filt->q_signed ? 128.0 * (double)filt->sum_int / D : 0.0));
+        j.q_bias = (float)(0.25 / D + (filt->q_signed ? 128.0 * (double)filt->sum_int / D : 0.0));
     }
     // float32 cells: the 6-product split keeps every product term down to
     // 2^-16 relative (about 1e-7 after rounding); Auto uses it.  The 3-product

@@ -27,10 +27,12 @@
 //    1 (k = 3) or 2 (k = 5, 7) dot products per output.
 //  * Input-stationary z ring of k partial sums per output; the z loop is
 //    unrolled by k so the ring slots are fixed registers.
-//  * Epilogue in FP32: floor(T/D + 1/2) = floor(T * (1/D) + 1/2 + 1/(4D)),
-//    one FMA; its rounding error stays below the 1/(4D) margin for the
-//    eligible sizes, so the result is the exact integer quotient.  Four
-//    saturated bytes go out as one dword store.
+//  * Epilogue in FP32: T/D + 1/2 is a multiple of 1/(2D), so
+//    floor(T/D + 1/2) = round-to-nearest(T * (1/D) + 1/(4D)) whenever the
+//    FMA's rounding error stays below 1/(4D), which the eligibility bounds
+//    guarantee (3 * 2^-24 * (256 sum|w| + D) < 1/4).  v_cvt_pk_u8_f32 does
+//    the rounding, the saturation to [0, 255] and the packing of four
+//    outputs into one dword store.
 #include "vkt_internal.h"
 
 #include <type_traits>
@@ -53,6 +55,7 @@ struct Geo4 {
     static constexpr int PLANE_BUF = PLANE + 4;         // + a dummy dword (padded)
     static constexpr int NH = (K + 3) / 4;              // weight dwords per filter row
     static constexpr int NROW = VY + K - 1;             // input rows per lane
+    static constexpr int WAVES = K <= 3 ? 4 : K <= 5 ? 3 : 2;  // occupancy target per SIMD
     static_assert(R <= 4, "one halo dword per side");
 };
 
@@ -162,19 +165,24 @@ __device__ void dot4_tile(const VolDesc& a, const uint32_t* __restrict__ wq, int
     // threads 0 .. 2 HY - 1.  A dword is loaded whole, except the one just
     // past either x face of the volume, whose four bytes go through the
     // address mode.  Interior dwords at or past the right face are not
-    // staged (they feed no stored output); slots with nothing to stage write
-    // a dummy LDS dword past the plane.
+    // staged (they feed no stored output); halo slots of threads with no row
+    // write a dummy LDS dword past the plane.
     constexpr int NI = (G::HY + kWaves - 1) / kWaves;  // interior slots per thread
-    uint32_t goff[NI + 1];  // byte offset of the dword (face dwords: of the row)
-    int32_t loff[NI + 1];   // LDS dword
+    const int wv_u = __builtin_amdgcn_readfirstlane(wave);  // wave-uniform copy
+    // interior slot i: row hy = wave + 4 i, a wave-uniform byte offset of the
+    // staged row's first interior dword (SGPR) plus 4 * lane (VGPR)
+    uint32_t srow[NI];
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
-        const int hy = wave + kWaves * i;
-        const int xb = x0 + 4 * lane;
+        const int hy = wv_u + kWaves * i;
         const int gy = hy < G::HY ? addr_map((int64_t)y0 - R + hy, a.Y, a.mode) : -1;
-        goff[i] = gy < 0 ? kOutside : (uint32_t)gy * (uint32_t)a.X + (uint32_t)xb;
-        loff[i] = (hy < G::HY && xb + 4 <= a.X) ? hy * G::WD + 1 + lane : G::PLANE;
+        srow[i] = gy < 0 ? kOutside : (uint32_t)gy * (uint32_t)a.X + (uint32_t)x0;
     }
+    const uint32_t vlane = 4u * (uint32_t)lane;
+    const bool xin = x0 + 4 * lane + 4 <= a.X;               // dword inside the volume
+    uint32_t* const lrow = lds + wave * G::WD + 1 + lane;    // slot 0's LDS dword (buffer 0)
+    uint32_t goff[NI + 1];  // [NI]: byte offset of the halo dword (face dwords: of the row)
+    int32_t loff[NI + 1];   // [NI]: its LDS dword
     // halo slot: row t / 2, left (even t) or right (odd t) neighbour dword
     bool face;
     int fside;
@@ -212,8 +220,9 @@ __device__ void dot4_tile(const VolDesc& a, const uint32_t* __restrict__ wq, int
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<char*>(base), (short)0, gz < 0 ? 0 : plane_bytes, (int)kRsrcWord3);
 #pragma unroll
-        for (int i = 0; i <= NI; ++i)
-            stage[i] = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)goff[i], 0, 0);
+        for (int i = 0; i < NI; ++i)
+            stage[i] = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)vlane, (int)srow[i], 0);
+        stage[NI] = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)goff[NI], 0, 0);
         if (face) {
             uint32_t v = 0;
 #pragma unroll
@@ -224,9 +233,13 @@ __device__ void dot4_tile(const VolDesc& a, const uint32_t* __restrict__ wq, int
             stage[NI] = v;
         }
     };
-    auto put = [&](uint32_t* buf) {
+    auto put = [&](int b) {
+        if (xin) {
 #pragma unroll
-        for (int i = 0; i <= NI; ++i) buf[loff[i]] = stage[i];
+            for (int i = 0; i < NI; ++i)
+                if (wv_u + kWaves * i < G::HY) lrow[b * G::PLANE_BUF + i * kWaves * G::WD] = stage[i];
+        }
+        lds[b * G::PLANE_BUF + loff[NI]] = stage[NI];
     };
 
     int32_t acc[K][VY][4];
@@ -239,8 +252,12 @@ __device__ void dot4_tile(const VolDesc& a, const uint32_t* __restrict__ wq, int
 
     const int zi_beg = zb - R;
     const int P = (ze - zb) + 2 * R;  // input planes of the slab
+    // planes 0 and 1 in flight before the first step; step p stages plane
+    // p + 1 (loaded during step p - 1) and issues the loads of plane p + 2,
+    // so a load has a whole step of taps to arrive
     gather(zi_beg);
-    put(lds);
+    put(0);
+    if (P > 1) gather(zi_beg + 1);
     __syncthreads();
 
     const int ox = x0 + 4 * lane;
@@ -250,53 +267,78 @@ __device__ void dot4_tile(const VolDesc& a, const uint32_t* __restrict__ wq, int
     // input plane p of the slab at ring position U = p mod k
     auto step = [&](int p, auto uc) {
         constexpr int U = decltype(uc)::value;
-        if (p + 1 < P) gather(zi_beg + p + 1);
+        if (p + 1 < P) put((p + 1) & 1);
+        if (p + 2 < P) gather(zi_beg + p + 2);
         const uint32_t* buf = lds + (p & 1) * G::PLANE_BUF + (wave * VY) * G::WD + lane;
 
-        // the 4 NH windows of every input row this lane needs
-        uint32_t win[G::NROW][4 * NH];
+        if constexpr (K <= 3) {
+            // stream the input rows: the 4 windows of row jr feed every
+            // (output row vy, filter row b = jr - vy, filter plane c)
 #pragma unroll
-        for (int jr = 0; jr < G::NROW; ++jr) {
-            uint32_t L = buf[jr * G::WD], C = buf[jr * G::WD + 1], Rr = buf[jr * G::WD + 2];
-            if constexpr (SG) {
-                L ^= 0x80808080u;
-                C ^= 0x80808080u;
-                Rr ^= 0x80808080u;
+            for (int jr = 0; jr < G::NROW; ++jr) {
+                uint32_t L = buf[jr * G::WD], C = buf[jr * G::WD + 1], Rr = buf[jr * G::WD + 2];
+                if constexpr (SG) {
+                    L ^= 0x80808080u;
+                    C ^= 0x80808080u;
+                    Rr ^= 0x80808080u;
+                }
+                uint32_t win[4];
+                static_for<4>([&](auto qc) {
+                    constexpr int j = decltype(qc)::value;
+                    win[j] = window<j - R>(L, C, Rr);
+                });
+                static_for<K>([&](auto cc) {
+                    constexpr int c = decltype(cc)::value;
+                    constexpr int slot = ((U - c) % K + K) % K;
+#pragma unroll
+                    for (int vy = 0; vy < VY; ++vy) {
+                        const int b = jr - vy;
+                        if (b < 0 || b >= K) continue;
+                        const uint32_t wrow = wq[(c * K + b) * NH];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            acc[slot][vy][j] = dot4<SG>(win[j], wrow, acc[slot][vy][j]);
+                    }
+                });
             }
-            static_for<4 * NH>([&](auto qc) {
-                constexpr int q = decltype(qc)::value;
-                constexpr int h = q / 4, j = q % 4;
-                win[jr][q] = window<j - R + 4 * h>(L, C, Rr);
+        } else {
+            // the 4 NH windows of every input row this lane needs, then one
+            // filter plane c (weights in SGPRs) at a time
+            uint32_t win[G::NROW][4 * NH];
+#pragma unroll
+            for (int jr = 0; jr < G::NROW; ++jr) {
+                uint32_t L = buf[jr * G::WD], C = buf[jr * G::WD + 1], Rr = buf[jr * G::WD + 2];
+                if constexpr (SG) {
+                    L ^= 0x80808080u;
+                    C ^= 0x80808080u;
+                    Rr ^= 0x80808080u;
+                }
+                static_for<4 * NH>([&](auto qc) {
+                    constexpr int q = decltype(qc)::value;
+                    constexpr int h = q / 4, j = q % 4;
+                    win[jr][q] = window<j - R + 4 * h>(L, C, Rr);
+                });
+            }
+            static_for<K>([&](auto cc) {
+                constexpr int c = decltype(cc)::value;
+                constexpr int slot = ((U - c) % K + K) % K;
+                uint32_t wv[16];
+                load_plane_weights(wq + c * K * NH, wv);
+#pragma unroll
+                for (int vy = 0; vy < VY; ++vy)
+#pragma unroll
+                    for (int b = 0; b < K; ++b)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+#pragma unroll
+                            for (int h = 0; h < NH; ++h)
+                                acc[slot][vy][j] = dot4<SG>(win[vy + b][4 * h + j], wv[b * NH + h],
+                                                            acc[slot][vy][j]);
+                // this plane's products complete before the next plane's
+                // weights are loaded (one weight group live in SGPRs)
+                pin8(acc[slot]);
             });
         }
-
-        // taps: filter plane c feeds ring slot (U - c) mod k
-        static_for<K>([&](auto cc) {
-            constexpr int c = decltype(cc)::value;
-            constexpr int slot = ((U - c) % K + K) % K;
-            uint32_t wv[16];
-            if constexpr (K <= 3) {
-#pragma unroll
-                for (int q = 0; q < K * NH; ++q) wv[q] = wq[c * K * NH + q];
-            } else {
-                load_plane_weights(wq + c * K * NH, wv);
-            }
-#pragma unroll
-            for (int vy = 0; vy < VY; ++vy)
-#pragma unroll
-                for (int b = 0; b < K; ++b)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-#pragma unroll
-                        for (int h = 0; h < NH; ++h)
-                            acc[slot][vy][j] =
-                                dot4<SG>(win[vy + b][4 * h + j], wv[b * NH + h], acc[slot][vy][j]);
-            // this plane's products complete before the next plane's weights
-            // are loaded (one weight group live in SGPRs)
-            if constexpr (K > 3) pin8(acc[slot]);
-        });
-
-        if (p + 1 < P) put(lds + ((p + 1) & 1) * G::PLANE_BUF);
 
         // output plane q = p - (k - 1) is complete in slot (U + 1) mod k
         constexpr int done = (U + 1) % K;
@@ -306,13 +348,13 @@ __device__ void dot4_tile(const VolDesc& a, const uint32_t* __restrict__ wq, int
             for (int vy = 0; vy < VY; ++vy) {
                 const int y = y0 + wave * VY + vy;
                 if (y >= a.Y) continue;
+                // v_cvt_pk_u8_f32 rounds to nearest even and saturates to
+                // [0, 255]; no result lies within 1/(4D) of a tie
                 uint32_t packed = 0;
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const float f = fmaf((float)acc[done][vy][j], inv_D, bias);
-                    const uint32_t q = (uint32_t)__builtin_amdgcn_fmed3f(f, 0.f, 255.f);
-                    packed |= q << (8 * j);
-                }
+                for (int j = 0; j < 4; ++j)
+                    packed = __builtin_amdgcn_cvt_pk_u8_f32(
+                        fmaf((float)acc[done][vy][j], inv_D, bias), j, packed);
                 *reinterpret_cast<uint32_t*>(dst + zo * plane + (int64_t)y * a.X + ox) = packed;
             }
         }
@@ -331,7 +373,8 @@ __device__ void dot4_tile(const VolDesc& a, const uint32_t* __restrict__ wq, int
 }
 
 template <int K, bool SG>
-__global__ __launch_bounds__(kNT) void filter_dot4_kernel(VolDesc a,
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(Geo4<K>::WAVES)))
+void filter_dot4_kernel(VolDesc a,
                                                           const uint32_t* __restrict__ wq,
                                                           uint32_t nblocks)
 {
@@ -344,7 +387,8 @@ __global__ __launch_bounds__(kNT) void filter_dot4_kernel(VolDesc a,
 // Persistent workgroups over a work queue of (volume, tile-slab) items; the
 // packed weights of all filters of the class are in the integer pool.
 template <int K, bool SG>
-__global__ __launch_bounds__(kNT) void filter_dot4_batched_kernel(BatchArgs b)
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(Geo4<K>::WAVES)))
+void filter_dot4_batched_kernel(BatchArgs b)
 {
     __shared__ __align__(16) uint32_t lds[2 * Geo4<K>::PLANE_BUF];
     __shared__ uint32_t s_item;

@@ -11,8 +11,8 @@
 //    through a z-slab of output planes.  Each input plane of the slab, with an
 //    r-wide halo in x and y, is gathered once (address mode applied to halo
 //    coordinates only, through per-thread 32-bit in-plane offsets computed once
-//    per tile) and staged in LDS as FP32 (or int32), double buffered; the next
-//    plane's loads are in flight while the current plane is computed.
+//    per tile) and staged in LDS as FP32 (or int32), double buffered; the
+//    loads of the plane after next are in flight while a plane is computed.
 //  * Input-stationary z ring: a thread owns 4 (x) x 2 (y) output columns and
 //    keeps k partial sums per output, one for each output plane zi - c + r the
 //    current input plane zi feeds.  A plane is read from LDS once per thread
@@ -219,17 +219,20 @@ __device__ void valu_tile(const VolDesc& a, const typename AccT<IACC>::type* __r
             for (int vx = 0; vx < kVX; ++vx) acc[c][vy][vx] = 0;
 
     const int zi_beg = zb - R, zi_end = ze + R;  // input planes [beg, end)
+    // planes zi_beg and zi_beg + 1 in flight before the loop; iteration zi
+    // stages plane zi + 1 (loaded during iteration zi - 1) and issues the
+    // loads of plane zi + 2, so a load has a whole plane of taps to arrive
     gather(zi_beg);
     put(lds);
+    if (zi_beg + 1 < zi_end) gather(zi_beg + 1);
     __syncthreads();
 
     const int ox = x0 + kVX * tx, oy = y0 + kVY * ty;
     const bool vec = a.vec_ok && ox + kVX <= a.X;
     for (int zi = zi_beg; zi < zi_end; ++zi) {
         const int cur = (zi - zi_beg) & 1;
-        // next plane's loads in flight during this plane's taps (the last
-        // iteration re-reads a valid plane and discards it)
-        gather(min(zi + 1, zi_end - 1));
+        if (zi + 1 < zi_end) put(lds + (cur ^ 1) * G::LDS_CELLS);
+        if (zi + 2 < zi_end) gather(zi + 2);
 
         const Acc* buf = lds + cur * G::LDS_CELLS + (kVY * ty) * G::P + kVX * tx;
         using V4 = typename std::conditional<IACC, int4, float4>::type;
@@ -294,8 +297,6 @@ __device__ void valu_tile(const VolDesc& a, const typename AccT<IACC>::type* __r
                 }
             }
         }
-
-        put(lds + (cur ^ 1) * G::LDS_CELLS);
 
         // ---- the ring's oldest entry is output plane zo = zi - r
         const int zo = zi - R;

@@ -111,7 +111,7 @@ struct VolDesc {
     float inv_D;
     int32_t vec_ok;
     float wscale, unscale;   // fp16 weight scaling of the matrix-core path
-    float bias;              // dot-product path: 1/2 + 1/(4D) (+ 128 sum(w) / D)
+    float bias;              // dot-product path: 1/(4D) (+ 128 sum(w) / D)
 };
 
 // One work item of a batched launch: a tile-slab of one volume.
