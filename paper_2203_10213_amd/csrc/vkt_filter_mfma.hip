@@ -25,9 +25,9 @@
 //
 // The four x-strips a wave owns are adjacent, so one 32-byte LDS read per
 // (row block, K chunk, operand piece) holds all four strips' 16-byte windows
-// (at dword offsets 0..3).  Finished outputs leave through raw buffer stores:
-// lanes that hold no finished output, and cells past the volume's edge, get
-// an out-of-range offset and their store is discarded.
+// (at dword offsets 0..3).  The finished column group of all of a wave's
+// tiles is an 8 x 64 block of outputs; it is transposed through LDS so that
+// each lane rounds and stores one row of 8 cells with one vector store.
 //
 // Split precision (16-bit operands, exact FP32 products, FP32 sums):
 //   uint8   voxels: exact in fp16 (1 piece) x weights in 2 fp16 pieces;
@@ -236,29 +236,65 @@ __device__ inline float shift_cols(float v, int lane)
     }
 }
 
-// Store one finished value (every lane stores; dropped lanes carry an
-// out-of-range offset).
-template <typename T>
-__device__ inline void store_out(__amdgpu_buffer_rsrc_t r, uint32_t voff, int soff, float t,
-                                 float unscale)
+// Round (integer cells) and store one lane's row of N finished outputs at
+// byte offset off: one vector store when the row lies inside the volume and
+// is 4-byte aligned, else cell stores for the first nx cells.  Dropped rows
+// carry an out-of-range offset.
+template <typename T, int N>
+__device__ inline void store_row(__amdgpu_buffer_rsrc_t r, uint32_t off, const float (&v)[N],
+                                 bool vec, int nx, float unscale)
 {
+    static_assert(N == 8, "8 cells per row");
     if constexpr (std::is_same<T, float>::value) {
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(t * unscale), r, (int)voff, soff, 0);
+        uint32_t u[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) u[i] = __float_as_uint(v[i] * unscale);
+        if (vec) {
+            __builtin_amdgcn_raw_buffer_store_b128(u32x4{u[0], u[1], u[2], u[3]}, r, (int)off, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b128(u32x4{u[4], u[5], u[6], u[7]}, r, (int)off + 16,
+                                                   0, 0);
+        } else {
+#pragma unroll
+            for (int i = 0; i < N; ++i)
+                __builtin_amdgcn_raw_buffer_store_b32(u[i], r, i < nx ? (int)(off + 4 * i) : (int)kOutside,
+                                                      0, 0);
+        }
     } else {
         constexpr float kMax = std::is_same<T, uint8_t>::value ? 255.f : 65535.f;
-        // floor(q + 1/2) saturated: truncation of a value clamped to [0, max]
-        const float q = __builtin_amdgcn_fmed3f(fmaf(t, unscale, 0.5f), 0.f, kMax);
-        const uint32_t u = (uint32_t)q;
-        if constexpr (sizeof(T) == 1)
-            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)u, r, (int)voff, soff, 0);
-        else
-            __builtin_amdgcn_raw_buffer_store_b16((uint16_t)u, r, (int)voff, soff, 0);
+        uint32_t u[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            // floor(q + 1/2) saturated: truncation of a value clamped to [0, max]
+            u[i] = (uint32_t)__builtin_amdgcn_fmed3f(fmaf(v[i], unscale, 0.5f), 0.f, kMax);
+        if (vec) {
+            if constexpr (sizeof(T) == 2) {
+                __builtin_amdgcn_raw_buffer_store_b128(
+                    u32x4{u[0] | (u[1] << 16), u[2] | (u[3] << 16), u[4] | (u[5] << 16),
+                          u[6] | (u[7] << 16)},
+                    r, (int)off, 0, 0);
+            } else {
+                typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+                __builtin_amdgcn_raw_buffer_store_b64(
+                    u32x2{u[0] | (u[1] << 8) | (u[2] << 16) | (u[3] << 24),
+                          u[4] | (u[5] << 8) | (u[6] << 16) | (u[7] << 24)},
+                    r, (int)off, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const int o = i < nx ? (int)(off + sizeof(T) * i) : (int)kOutside;
+                if constexpr (sizeof(T) == 2)
+                    __builtin_amdgcn_raw_buffer_store_b16((uint16_t)u[i], r, o, 0, 0);
+                else
+                    __builtin_amdgcn_raw_buffer_store_b8((uint8_t)u[i], r, o, 0, 0);
+            }
+        }
     }
 }
 
 template <class C>
 __device__ void mfma_tile(const VolDesc& a, const float* __restrict__ w, int tile, int slab,
-                          uint16_t* lds_base)
+                          uint16_t* lds_base, float* epi)
 {
     using T = typename C::Tin;
     using PC = typename C::PC;
@@ -334,22 +370,20 @@ __device__ void mfma_tile(const VolDesc& a, const float* __restrict__ w, int til
             for (int ps = 0; ps < PC::PS; ++ps) lds[buf][ps][loff[i]] = stage[i][ps];
     };
 
-    // ---- output offsets: lane's first finished row of each M tile, or kOutside
-    const int jcol = lane % M::NT;
+    // ---- output block of the wave: its finished columns form an 8 (x) by
+    // 64 (y) block; lanes holding a finished column write it to the wave's
+    // LDS block (y fastest), then lane l reads row l and stores its 8 cells
+    constexpr int BX = C::WS * C::NX, BY = C::SY * M::MT;
+    static_assert(BX == 8 && BY == 64, "one output row of 8 cells per lane");
+    const int jcol = lane % M::NT, gq = lane / M::NT;
     const int xo = jcol - (K - 1) * C::NX;  // finished column group k-1
-    const int row0 = 4 * (lane / M::NT);
-    uint32_t ooff[C::MTW];
-#pragma unroll
-    for (int m = 0; m < C::MTW; ++m) {
-        const int strip = wave * C::WS + m % C::WS, yb = m / C::WS;
-        const int x = x0 + C::NX * strip + xo;
-        const int y = y0 + yb * M::MT + row0;
-        // rows past the volume's last row fall beyond the plane: dropped too
-        ooff[m] = (xo >= 0 && xo < C::NX && x < a.X)
-                      ? ((uint32_t)y * (uint32_t)a.X + (uint32_t)x) * (uint32_t)sizeof(T)
-                      : kOutside;
-    }
-    const int row_bytes = a.X * (int)sizeof(T);
+    const bool fin = xo >= 0 && xo < C::NX;
+    float* const blk = epi + wave * BX * BY;
+    const int xw = x0 + BX * wave, yl = y0 + lane;
+    // rows past the volume's last row fall beyond the plane: dropped
+    const uint32_t ooff =
+        yl < a.Y ? ((uint32_t)yl * (uint32_t)a.X + (uint32_t)xw) * (uint32_t)sizeof(T) : kOutside;
+    const bool vec_row = a.vec_ok && xw + BX <= a.X;
 
     acc_t acc[C::MTW];
 #pragma unroll
@@ -370,36 +404,53 @@ __device__ void mfma_tile(const VolDesc& a, const float* __restrict__ w, int til
         const int cur = (zi - zi_beg) & 1;
         gather(min(zi + 1, zi_end - 1));
 
+        // (row block, K chunk) groups, software pipelined: the LDS segments
+        // of group g + 1 are read while group g's products issue
+        constexpr int NG = C::SY * C::NCH;
+        u32x4 seg[2][PC::PS][C::NRD];
+        auto load_seg = [&](int g, u32x4 (&sg)[PC::PS][C::NRD]) {
+            const int yb = g / C::NCH, q = g % C::NCH;
+            int b = C::SHAPE == 16 ? q * 4 + ag : q;
+            if (b > K - 1) b = K - 1;  // zero weights there; keep A finite
+            const int row = yb * M::MT + ai + b;
+            // one segment per piece holds the windows of the wave's strips
 #pragma unroll
-        for (int yb = 0; yb < C::SY; ++yb) {
+            for (int ps = 0; ps < PC::PS; ++ps)
 #pragma unroll
-            for (int q = 0; q < C::NCH; ++q) {
-                int b = C::SHAPE == 16 ? q * 4 + ag : q;
-                if (b > K - 1) b = K - 1;  // zero weights there; keep A finite
-                const int row = yb * M::MT + ai + b;
-                // one segment per piece holds the windows of the wave's strips
-                u32x4 seg[PC::PS][C::NRD];
+                for (int h = 0; h < C::NRD; ++h)
+                    sg[ps][h] = *reinterpret_cast<const u32x4*>(
+                        &lds[cur][ps][row * C::PITCH + acol + 8 * h]);
+        };
+        // (float32 volumes on 32x32 tiles, short of registers, read each
+        // group's segments just before its products: measured faster there)
+        constexpr bool PIPE = C::SHAPE == 16 || std::is_same<T, uint16_t>::value;
+        load_seg(0, seg[0]);
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            if constexpr (PIPE) {
+                if (g + 1 < NG) load_seg(g + 1, seg[(g + 1) & 1]);
+                // keep those reads ahead of this group's products
+                __builtin_amdgcn_sched_barrier(0);
+            } else {
+                if (g > 0) load_seg(g, seg[g & 1]);
+            }
+            const int yb = g / C::NCH, q = g % C::NCH;
+            // strip s's window: dwords s .. s+3 of the segment
+            u32x4 A[C::WS][PC::PS];
+#pragma unroll
+            for (int st = 0; st < C::WS; ++st)
 #pragma unroll
                 for (int ps = 0; ps < PC::PS; ++ps)
 #pragma unroll
-                    for (int h = 0; h < C::NRD; ++h)
-                        seg[ps][h] = *reinterpret_cast<const u32x4*>(
-                            &lds[cur][ps][row * C::PITCH + acol + 8 * h]);
+                    for (int d = 0; d < 4; ++d)
+                        A[st][ps][d] = seg[g & 1][ps][(st + d) / 4][(st + d) % 4];
+            // products outer, strips inner: consecutive MFMAs are independent
 #pragma unroll
-                for (int s = 0; s < C::WS; ++s) {
-                    // strip s's window: dwords s .. s+3 of the segment
-                    u32x4 A[PC::PS];
+            for (int pr = 0; pr < PC::NPROD; ++pr)
 #pragma unroll
-                    for (int ps = 0; ps < PC::PS; ++ps)
-#pragma unroll
-                        for (int d = 0; d < 4; ++d)
-                            A[ps][d] = seg[ps][(s + d) / 4][(s + d) % 4];
-                    acc_t& c = acc[yb * C::WS + s];
-#pragma unroll
-                    for (int pr = 0; pr < PC::NPROD; ++pr)
-                        c = mfma<C::SHAPE, PC::F16>(A[PC::prod[pr][0]], B[q][PC::prod[pr][1]], c);
-                }
-            }
+                for (int st = 0; st < C::WS; ++st)
+                    acc[yb * C::WS + st] = mfma<C::SHAPE, PC::F16>(
+                        A[st][PC::prod[pr][0]], B[q][PC::prod[pr][1]], acc[yb * C::WS + st]);
         }
 
         put(cur ^ 1);
@@ -407,16 +458,28 @@ __device__ void mfma_tile(const VolDesc& a, const float* __restrict__ w, int til
         // ---- column group k-1 holds output plane zi - r
         const int zo = zi - R;
         if (zo >= zb) {
+            if (fin) {
+#pragma unroll
+                for (int m = 0; m < C::MTW; ++m) {
+                    const int yb = m / C::WS, st = m % C::WS;
+                    float* col = blk + (st * C::NX + xo) * BY + yb * M::MT + 4 * gq;
+#pragma unroll
+                    for (int qd = 0; qd < M::NACC / 4; ++qd)
+                        *reinterpret_cast<f32x4*>(col + 8 * qd) =
+                            f32x4{acc[m][4 * qd], acc[m][4 * qd + 1], acc[m][4 * qd + 2],
+                                  acc[m][4 * qd + 3]};
+                }
+            }
+            // the wave's own LDS writes complete before its lanes read them
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+            float v[BX];
+#pragma unroll
+            for (int xl = 0; xl < BX; ++xl) v[xl] = blk[xl * BY + lane];
             const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(
                 static_cast<char*>(a.dst) + (int64_t)zo * plane_bytes, (short)0, plane_bytes,
                 (int)kRsrcWord3);
-#pragma unroll
-            for (int m = 0; m < C::MTW; ++m)
-#pragma unroll
-                for (int r = 0; r < M::NACC; ++r) {
-                    const int drow = C::SHAPE == 16 ? r : 8 * (r / 4) + (r % 4);
-                    store_out<T>(rd, ooff[m], drow * row_bytes, acc[m][r], a.unscale);
-                }
+            store_row<T, BX>(rd, ooff, v, vec_row, a.X - xw, a.unscale);
+            asm volatile("" ::: "memory");
         }
         // ---- advance the ring
 #pragma unroll
@@ -432,6 +495,8 @@ constexpr int lds_elems()
 {
     return 2 * C::PC::PS * C::HY * C::PITCH;
 }
+// output transposition blocks: 4 waves x 8 x 64 floats
+constexpr int kEpiFloats = 4 * 8 * 64;
 
 template <class C>
 __global__ __launch_bounds__(kNT, 1) void filter_mfma_kernel(VolDesc a,
@@ -439,9 +504,10 @@ __global__ __launch_bounds__(kNT, 1) void filter_mfma_kernel(VolDesc a,
                                                              uint32_t nblocks)
 {
     __shared__ __align__(16) uint16_t lds[lds_elems<C>()];
+    __shared__ __align__(16) float epi[kEpiFloats];
     const uint32_t lid = xcd_remap(blockIdx.x, nblocks);
     const uint32_t ntiles = (uint32_t)a.tiles_x * (uint32_t)a.tiles_y;
-    mfma_tile<C>(a, w, (int)(lid % ntiles), (int)(lid / ntiles), lds);
+    mfma_tile<C>(a, w, (int)(lid % ntiles), (int)(lid / ntiles), lds, epi);
 }
 
 // Persistent workgroups over a queue of (volume, tile-slab) items; the last
@@ -450,6 +516,7 @@ template <class C>
 __global__ __launch_bounds__(kNT, 1) void filter_mfma_batched_kernel(BatchArgs b)
 {
     __shared__ __align__(16) uint16_t lds[lds_elems<C>()];
+    __shared__ __align__(16) float epi[kEpiFloats];
     __shared__ uint32_t s_item;
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(&b.counters[0], 1u);
@@ -460,7 +527,8 @@ __global__ __launch_bounds__(kNT, 1) void filter_mfma_batched_kernel(BatchArgs b
         const WorkItem wi = b.items[it];
         const VolDesc a = b.vols[wi.vol];
         const uint32_t ntiles = (uint32_t)a.tiles_x * (uint32_t)a.tiles_y;
-        mfma_tile<C>(a, b.wpool + a.woff, (int)(wi.lid % ntiles), (int)(wi.lid / ntiles), lds);
+        mfma_tile<C>(a, b.wpool + a.woff, (int)(wi.lid % ntiles), (int)(wi.lid / ntiles), lds,
+                     epi);
     }
     if (threadIdx.x == 0) {
         __threadfence();
