@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2",
-                    choices=["c1", "c2", "c2a", "c2b", "c3a", "c3b", "c5"])
+                    choices=["c1", "c2", "c2a", "c2b", "c3a", "c3b", "c4", "c5"])
     ap.add_argument("--precision", default=None,
                     choices=["auto", "fp32", "splitbf16", "splitbf16x6"],
                     help="default: fp32 for c1/c2 (the plain-path configurations), "
@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample")
+    ap.add_argument("--autotune", action="store_true",
+                    help="c4: let the batched planner time its slab-depth candidates")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -232,6 +234,83 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes": n, "launches": 3}))
 
 
+def run_batched(args, vkt, torch):
+    """The batched workload: 256 uint16 volumes of uneven sizes, k in {3,5,7}
+    Gaussians, one vktApplyFilterBatched (persistent kernels, replayed
+    hipGraph) per step; the same work as 256 single launches is timed beside
+    it.  Returns the bench line."""
+    from paper_2203_10213_amd import synth
+    vols, ks = synth.gamma_u16_volumes(256, synth.SEEDS["c4"])
+    filts = {k: vkt.vktFilterCreate(synth.gaussian_weights(k, k / 4)) for k in (3, 5, 7)}
+    srcs = [torch.from_numpy(v).cuda() for v in vols]
+    dsts = [torch.empty_like(x) for x in srcs]
+    hs = [vkt.volume_from_tensor(x) for x in srcs]
+    hd = [vkt.volume_from_tensor(x) for x in dsts]
+    hf = [filts[k] for k in ks]
+    stream = torch.cuda.current_stream()
+    vkt.vktSetAutotune(args.autotune)
+    torch.cuda.synchronize()
+
+    def batched():
+        vkt.vktApplyFilterBatched(hd, hs, hf, "clamp")
+
+    def singles():
+        for i in range(len(hs)):
+            vkt.vktApplyFilter(hd[i], hs[i], hf[i], vkt.vktAddressModeClamp)
+
+    def timed(fn, K, W):
+        for _ in range(W):
+            fn()
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for _ in range(K):
+            fn()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1) / K
+
+    print(f"[bench] c4 batched, warmup {args.warmup}", file=sys.stderr, flush=True)
+    ms_b = timed(batched, args.steps, args.warmup)
+    print("[bench] c4 single launches", file=sys.stderr, flush=True)
+    ms_s = timed(singles, max(1, args.steps // 2), 1)
+    voxels = sum(int(v.size) for v in vols)
+    flops = sum(int(v.size) * 2 * k ** 3 for v, k in zip(vols, ks))
+    bytes_alg = 4 * voxels
+    t = ms_b * 1e-3
+    # the step's binding roofline: the split-fp16 matrix path carries the
+    # k = 5, 7 volumes (most of the flops); all volumes move 4 bytes per cell
+    mfma_flops = sum(int(v.size) * 2 * k ** 3 for v, k in zip(vols, ks) if k >= 5)
+    roof = {"bound": "mfma", "achieved": mfma_flops / t / 1e12, "peak": BF16_MFMA_PEAK_TF,
+            "unit": "TFLOP/s", "frac": mfma_flops / t / 1e12 / BF16_MFMA_PEAK_TF,
+            "traffic": None, "kernel_case": "c4 k>=5 classes (one graph launch)"}
+    line = {
+        "metric": "Gvoxels/s ApplyFilter on 1 MI355X",
+        "value": voxels / t / 1e9, "unit": "Gvoxels/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_b, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f16x2->f32+f32",
+        "data": "synthetic",
+        "config": {"workload": "c4", "cases": ["256 u16 volumes, axes U{32..256}, "
+                                               "Gaussian k in {3,5,7}, sigma k/4"],
+                   "address_mode": "clamp", "precision": args.precision,
+                   "autotune": bool(args.autotune)},
+        "roofline": roof,
+        "cpu_baseline": None,
+        "per_case": [{"case": "c4_batched_graph", "ms": ms_b, "gvoxels_s": voxels / t / 1e9,
+                      "hbm_frac": bytes_alg / t / 1e9 / HBM_PEAK_GBS, "tflops": flops / t / 1e12},
+                     {"case": "c4_256_single_launches", "ms": ms_s,
+                      "gvoxels_s": voxels / (ms_s * 1e-3) / 1e9,
+                      "hbm_frac": bytes_alg / (ms_s * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                      "tflops": flops / (ms_s * 1e-3) / 1e12}],
+    }
+    for h in hs + hd:
+        vkt.vktStructuredVolumeDestroy(h)
+    for f in filts.values():
+        vkt.vktFilterDestroy(f)
+    return line
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -251,13 +330,16 @@ def main():
         return
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    print(f"[bench] building inputs for {args.workload}", file=sys.stderr, flush=True)
-    cases = make_cases(args.workload, dev)
     if args.precision is None:
         args.precision = "fp32" if args.workload in ("c1", "c2", "c2a", "c2b") else "auto"
     stream = torch.cuda.current_stream()
     vkt.vktSetStream(stream)
     vkt.vktSetPrecision(args.precision)
+    if args.workload == "c4":
+        print(json.dumps(run_batched(args, vkt, torch)))
+        return
+    print(f"[bench] building inputs for {args.workload}", file=sys.stderr, flush=True)
+    cases = make_cases(args.workload, dev)
     for c in cases:
         c["path"] = kernel_path(c, args.precision)
         c["dst"] = torch.empty_like(c["src"])
