@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <unordered_set>
 #include <vector>
@@ -329,6 +330,47 @@ const void* mfma_batched_kernel(vktDataFormat f, int k, bool six_products)
 }
 
 ClassGeom mfma_geom(int k) { return k <= 7 ? mfma_geom_s16(k) : mfma_geom_s32(k); }
+
+int resident_wgs(const void* func)
+{
+    static std::mutex mu;
+    static std::map<std::pair<const void*, int>, int> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find({func, dev});
+    if (it != cache.end()) return it->second;
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, func, 256, 0) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+        cus = 1;
+    const int n = per_cu * cus;
+    cache[{func, dev}] = n;
+    return n;
+}
+
+int plan_tz(int64_t ntiles, int Z, int k, int tz_min, int tz_max, int slots, int mod)
+{
+    if (Z <= tz_min) return Z;
+    if (tz_max > Z) tz_max = Z;
+    if (tz_max < tz_min) tz_max = tz_min;
+    int best = tz_max;
+    double best_cost = -1.0;
+    for (int tz = tz_min; tz <= tz_max; ++tz) {
+        if (mod > 1 && tz % mod != 1 % mod && tz != Z) continue;
+        const int64_t nwg = ntiles * ((Z + tz - 1) / tz);
+        const int64_t rounds = (nwg + slots - 1) / slots;
+        const double cost = (double)rounds * (tz + k - 1);
+        if (best_cost < 0.0 || cost < best_cost) {  // ties keep the smaller tz
+            best_cost = cost;
+            best = tz;
+        }
+    }
+    return best;
+}
 
 UDiv make_udiv(uint32_t d)
 {

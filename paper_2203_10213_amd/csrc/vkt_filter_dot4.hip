@@ -418,14 +418,9 @@ hipError_t launch_k(const FilterJob& j, hipStream_t s)
 {
     const ClassGeom g = dot4_geom(K);
     const int64_t ntiles = (int64_t)((j.X + g.tx - 1) / g.tx) * ((j.Y + g.ty - 1) / g.ty);
-    // z-slab depth: enough workgroups to fill 256 CUs several times over,
-    // slabs deep enough to amortise the 2r halo planes
-    const int64_t want_slabs = (2048 + ntiles - 1) / ntiles;
-    int tz = (int)((j.Z + want_slabs - 1) / want_slabs);
-    if (tz < g.tz_min) tz = g.tz_min;
-    if (tz > 64) tz = 64;
-    tz += ((1 - tz) % K + K) % K;  // tz = 1 mod k: tz + k - 1 input planes, whole ring turns
-    if (tz > j.Z) tz = j.Z;
+    // tz = 1 mod k: the slab's tz + k - 1 input planes are whole ring turns
+    const void* fn = (const void*)&filter_dot4_kernel<K, SG>;
+    const int tz = plan_tz(ntiles, j.Z, K, g.tz_min, 128, resident_wgs(fn), K);
     const VolDesc a = make_desc(j, tz, g);
     const int64_t nb = ntiles * ((j.Z + tz - 1) / tz);
     if (nb > 0x7fffffff) return hipErrorInvalidValue;

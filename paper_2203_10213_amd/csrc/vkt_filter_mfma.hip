@@ -562,13 +562,10 @@ hipError_t launch_cfg(const FilterJob& j, hipStream_t s)
 {
     const ClassGeom g = geom_here(j.k);
     const int64_t ntiles = (int64_t)((j.X + g.tx - 1) / g.tx) * ((j.Y + g.ty - 1) / g.ty);
-    // z-slab depth: enough workgroups for several waves of the device, slabs
-    // deep enough that the k-1 ring warm-up planes cost little
-    const int64_t want_slabs = (2048 + ntiles - 1) / ntiles;
-    int tz = (int)((j.Z + want_slabs - 1) / want_slabs);
-    if (tz < g.tz_min) tz = g.tz_min;
-    if (tz > 128) tz = 128;
-    if (tz > j.Z) tz = j.Z;
+    const void* fn = (const void*)&filter_mfma_kernel<C>;
+    // (deeper slabs measured slower for the 16x16 tiles, faster for 32x32)
+    const int tz = plan_tz(ntiles, j.Z, j.k, g.tz_min, C::SHAPE == 16 ? 128 : 512,
+                           resident_wgs(fn), 1);
     const VolDesc a = make_desc(j, tz, g);
     const int64_t nb = ntiles * ((j.Z + tz - 1) / tz);
     if (nb > 0x7fffffff) return hipErrorInvalidValue;

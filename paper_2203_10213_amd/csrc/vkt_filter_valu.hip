@@ -387,13 +387,8 @@ hipError_t launch_k(const FilterJob& j, hipStream_t s)
 {
     const ClassGeom g = valu_geom(K);
     const int64_t ntiles = (int64_t)((j.X + g.tx - 1) / g.tx) * ((j.Y + g.ty - 1) / g.ty);
-    // z-slab depth: enough workgroups to fill 256 CUs several times over,
-    // slabs deep enough to amortise the 2r halo planes
-    const int64_t want_slabs = (2048 + ntiles - 1) / ntiles;
-    int tz = (int)((j.Z + want_slabs - 1) / want_slabs);
-    if (tz < g.tz_min) tz = g.tz_min;
-    if (tz > 64) tz = 64;
-    if (tz > j.Z) tz = j.Z;
+    const void* fn = (const void*)&filter_valu_kernel<T, K, IACC>;
+    const int tz = plan_tz(ntiles, j.Z, K, g.tz_min, 128, resident_wgs(fn), 1);
     const VolDesc a = make_desc(j, tz, g);
     const int64_t nb = ntiles * ((j.Z + tz - 1) / tz);
     if (nb > 0x7fffffff) return hipErrorInvalidValue;

@@ -172,6 +172,14 @@ const void* mfma_batched_kernel(vktDataFormat f, int k, bool six_products);
 ClassGeom mfma_geom(int k);
 // Fill in the descriptor fields the kernels derive from a FilterJob.
 VolDesc make_desc(const FilterJob& j, int tz, ClassGeom g);
+// Workgroups of 256 threads of `func` resident on the whole current device
+// at once (occupancy x compute units), cached per (kernel, device).
+int resident_wgs(const void* func);
+// Z-slab depth of a single-volume launch of ntiles tiles per plane: the
+// depth in [tz_min, tz_max] (tz = 1 mod `mod` when mod > 1) that minimises
+// rounds x (tz + k - 1), where a round is one wave of `slots` resident
+// workgroups and tz + k - 1 input planes are streamed per tile-slab.
+int plan_tz(int64_t ntiles, int Z, int k, int tz_min, int tz_max, int slots, int mod);
 
 // Validation and planning shared by the single and batched calls: fills j
 // and the chosen path (mfma, six products) for one (dst, src, filter) triple.
