@@ -251,7 +251,8 @@ __device__ void dot4_tile(const VolDesc& a, const uint32_t* __restrict__ wq, int
             for (int j = 0; j < 4; ++j) acc[c][vy][j] = 0;
 
     const int zi_beg = zb - R;
-    const int P = (ze - zb) + 2 * R;  // input planes of the slab
+    const int nz = ze - zb;           // output planes of the slab
+    const int P = nz + 2 * R;         // input planes of the slab
     // planes 0 and 1 in flight before the first step; step p stages plane
     // p + 1 (loaded during step p - 1) and issues the loads of plane p + 2,
     // so a load has a whole step of taps to arrive
@@ -290,6 +291,9 @@ __device__ void dot4_tile(const VolDesc& a, const uint32_t* __restrict__ wq, int
                 static_for<K>([&](auto cc) {
                     constexpr int c = decltype(cc)::value;
                     constexpr int slot = ((U - c) % K + K) % K;
+                    // filter plane c feeds output plane p - c of the slab:
+                    // skip planes outside it (never stored)
+                    if (p - c < 0 || p - c >= nz) return;
 #pragma unroll
                     for (int vy = 0; vy < VY; ++vy) {
                         const int b = jr - vy;

@@ -235,6 +235,9 @@ __device__ void valu_tile(const VolDesc& a, const typename AccT<IACC>::type* __r
         if (zi + 2 < zi_end) gather(zi + 2);
 
         const Acc* buf = lds + cur * G::LDS_CELLS + (kVY * ty) * G::P + kVX * tx;
+        // ring slot c feeds output plane zi - c + r; slots outside the slab's
+        // output planes [zb, ze) are never stored, so their taps are skipped
+        const int c_lo = max(0, zi + R - ze + 1), c_hi = min(K - 1, zi + R - zb);
         using V4 = typename std::conditional<IACC, int4, float4>::type;
         if constexpr (K <= 3) {
             // all (2 + k - 1) row windows in registers, then the taps of one
@@ -252,6 +255,7 @@ __device__ void valu_tile(const VolDesc& a, const typename AccT<IACC>::type* __r
                 }
 #pragma unroll
             for (int c = 0; c < K; ++c) {
+                if (c < c_lo || c > c_hi) continue;
                 constexpr int NW = sload_width(K * K);
                 Acc wv[NW];
                 load_weights<NW>(w + c * K * K, wv);
@@ -285,6 +289,7 @@ __device__ void valu_tile(const VolDesc& a, const typename AccT<IACC>::type* __r
                     if (b < 0 || b >= K) continue;
 #pragma unroll
                     for (int c = 0; c < K; ++c) {
+                        if (c < c_lo || c > c_hi) continue;
                         constexpr int NW = sload_width(K);
                         Acc wv[NW];
                         load_weights<NW>(w + (c * K + b) * K, wv);
