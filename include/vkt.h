@@ -162,6 +162,21 @@ vktError vktFillRangeSV(vktStructuredVolume volume, int32_t firstX,
 vktError vktApplyFilter(vktStructuredVolume dst, vktStructuredVolume src,
                         vktFilter filter, vktAddressMode mode);
 
+/* Range version (paper Sec. 3.2: algorithms come with a Range variant that
+ * operates on an axis-aligned region of interest given in cell
+ * coordinates).  Writes only the cells of dst inside the half-open ROI
+ * [first, last) -- the same bounds convention as vktFillRange -- with the
+ * values vktApplyFilter would store there; every other cell of dst keeps its
+ * contents.  The source is addressed through the whole volume and the
+ * address mode (cells just outside the ROI are read, not replaced by the
+ * address mode).  An empty ROI (first == last on some axis) enqueues nothing.
+ * Errors: as vktApplyFilter; vktInvalidValue when first > last or last
+ * exceeds the dims on some axis, or a coordinate is negative. */
+vktError vktApplyFilterRange(vktStructuredVolume dst, vktStructuredVolume src,
+                             vktFilter filter, int32_t firstX, int32_t firstY,
+                             int32_t firstZ, int32_t lastX, int32_t lastY,
+                             int32_t lastZ, vktAddressMode mode);
+
 /* Batched form: dst[i] = ApplyFilter(src[i], filters[i]) for i < n, each
  * pair exactly as vktApplyFilter would compute it, for volumes of different
  * sizes and filters of different k.  The pairs are grouped into arithmetic

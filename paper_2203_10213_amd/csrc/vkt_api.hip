@@ -236,8 +236,14 @@ VolDesc make_desc(const FilterJob& j, int tz, ClassGeom g)
     a.Z = j.Z;
     a.mode = j.mode;
     a.tz = tz;
-    a.tiles_x = (j.X + g.tx - 1) / g.tx;
-    a.tiles_y = (j.Y + g.ty - 1) / g.ty;
+    a.rx0 = j.roi[0];
+    a.ry0 = j.roi[1];
+    a.rz0 = j.roi[2];
+    a.rx1 = j.roi[3];
+    a.ry1 = j.roi[4];
+    a.rz1 = j.roi[5];
+    a.tiles_x = (a.rx1 - a.rx0 + g.tx - 1) / g.tx;
+    a.tiles_y = (a.ry1 - a.ry0 + g.ty - 1) / g.ty;
     a.woff = 0;
     if (j.fmt == vktDataFormatFloat32) a.epi = j.int_filter ? kEpiFloatDiv : kEpiFloat;
     else a.epi = j.int_filter ? kEpiIntDiv : kEpiRound;
@@ -253,7 +259,7 @@ VolDesc make_desc(const FilterJob& j, int tz, ClassGeom g)
 
 vktError build_job(const vktStructuredVolume_* dst, const vktStructuredVolume_* src,
                    const vktFilter_* filt, int mode, vktPrecision prec, FilterJob& j,
-                   bool& mfma, bool& six)
+                   bool& mfma, bool& six, const int32_t* roi)
 {
     if (!live_volume(dst) || !live_volume(src) || !live_filter(filt)) return vktInvalidValue;
     if (mode < vktAddressModeClamp || mode > vktAddressModeBorder) return vktInvalidValue;
@@ -274,6 +280,8 @@ vktError build_job(const vktStructuredVolume_* dst, const vktStructuredVolume_* 
     j.X = src->dims[0];
     j.Y = src->dims[1];
     j.Z = src->dims[2];
+    const int32_t whole[6] = {0, 0, 0, j.X, j.Y, j.Z};
+    std::memcpy(j.roi, roi ? roi : whole, sizeof(j.roi));
     j.mode = mode;
     j.fmt = src->fmt;
     j.k = filt->k;
@@ -291,7 +299,9 @@ vktError build_job(const vktStructuredVolume_* dst, const vktStructuredVolume_* 
         j.int_acc = filt->sum_abs_int * mx >= (int64_t(1) << 24);
         j.div2D = make_udiv(2u * (uint32_t)filt->divisor);
     }
-    j.vec_store = (j.X % 4 == 0) &&
+    // 4-cell vector stores: rows, the region's first column and the buffer
+    // 4-cell aligned
+    j.vec_store = (j.X % 4 == 0) && (j.roi[0] % 4 == 0) &&
                   (reinterpret_cast<uintptr_t>(dst->dev) % (4 * cell_bytes(src->fmt)) == 0);
     j.wscale = filt->wscale;
     // Plan: float-weight filters with k >= 5 run on the matrix cores unless
@@ -300,6 +310,7 @@ vktError build_job(const vktStructuredVolume_* dst, const vktStructuredVolume_* 
     // small integer weights as 8-bit dot products (4-byte rows and buffers).
     mfma = !filt->is_int && filt->k >= 5 && prec != vktPrecisionFP32;
     j.dot4 = filt->q_ok && src->fmt == vktDataFormatUInt8 && j.X % 4 == 0 &&
+             j.roi[0] % 4 == 0 && j.roi[3] % 4 == 0 &&
              reinterpret_cast<uintptr_t>(src->dev) % 4 == 0 &&
              reinterpret_cast<uintptr_t>(dst->dev) % 4 == 0;
     j.q_signed = filt->q_signed;
@@ -507,6 +518,25 @@ vktError vktApplyFilter(vktStructuredVolume dst, vktStructuredVolume src, vktFil
     bool mfma = false, six = false;
     const vktError e = vkt::build_job(dst, src, filt, mode, state().precision, j, mfma, six);
     if (e != vktNoError) return e;
+    if (mfma) return from_hip(vkt::launch_filter_mfma(j, six, state().stream));
+    if (j.dot4) return from_hip(vkt::launch_filter_dot4(j, state().stream));
+    return from_hip(vkt::launch_filter_valu(j, state().stream));
+}
+
+vktError vktApplyFilterRange(vktStructuredVolume dst, vktStructuredVolume src, vktFilter filt,
+                             int32_t x0, int32_t y0, int32_t z0, int32_t x1, int32_t y1,
+                             int32_t z1, vktAddressMode mode)
+{
+    if (!vkt::live_volume(src)) return vktInvalidValue;
+    const int32_t roi[6] = {x0, y0, z0, x1, y1, z1};
+    for (int a = 0; a < 3; ++a)
+        if (roi[a] < 0 || roi[a] > roi[a + 3] || roi[a + 3] > src->dims[a]) return vktInvalidValue;
+    vkt::FilterJob j;
+    bool mfma = false, six = false;
+    const vktError e =
+        vkt::build_job(dst, src, filt, mode, state().precision, j, mfma, six, roi);
+    if (e != vktNoError) return e;
+    if (x0 == x1 || y0 == y1 || z0 == z1) return vktNoError;  // empty region
     if (mfma) return from_hip(vkt::launch_filter_mfma(j, six, state().stream));
     if (j.dot4) return from_hip(vkt::launch_filter_dot4(j, state().stream));
     return from_hip(vkt::launch_filter_valu(j, state().stream));

@@ -155,8 +155,8 @@ __device__ void dot4_tile(const VolDesc& a, const uint32_t* __restrict__ wq, int
     uint8_t* __restrict__ dst = static_cast<uint8_t*>(a.dst);
 
     const int t = threadIdx.x, lane = t % kLanes, wave = t / kLanes;
-    const int x0 = (tile % a.tiles_x) * kTX, y0 = (tile / a.tiles_x) * G::TY;
-    const int zb = slab * a.tz, ze = min(zb + a.tz, a.Z);
+    const int x0 = a.rx0 + (tile % a.tiles_x) * kTX, y0 = a.ry0 + (tile / a.tiles_x) * G::TY;
+    const int zb = a.rz0 + slab * a.tz, ze = min(zb + a.tz, a.rz1);
     const int64_t plane = (int64_t)a.X * a.Y;
 
     // Staged dwords, the same (x, y) for every plane of the slab.  Interior
@@ -262,7 +262,7 @@ __device__ void dot4_tile(const VolDesc& a, const uint32_t* __restrict__ wq, int
     __syncthreads();
 
     const int ox = x0 + 4 * lane;
-    const bool x_ok = ox < a.X;
+    const bool x_ok = ox < a.rx1;  // rx1 is a multiple of 4
     const float inv_D = a.inv_D, bias = a.bias;
 
     // input plane p of the slab at ring position U = p mod k
@@ -351,7 +351,7 @@ __device__ void dot4_tile(const VolDesc& a, const uint32_t* __restrict__ wq, int
 #pragma unroll
             for (int vy = 0; vy < VY; ++vy) {
                 const int y = y0 + wave * VY + vy;
-                if (y >= a.Y) continue;
+                if (y >= a.ry1) continue;
                 // v_cvt_pk_u8_f32 rounds to nearest even and saturates to
                 // [0, 255]; no result lies within 1/(4D) of a tie
                 uint32_t packed = 0;
@@ -421,12 +421,14 @@ template <int K, bool SG>
 hipError_t launch_k(const FilterJob& j, hipStream_t s)
 {
     const ClassGeom g = dot4_geom(K);
-    const int64_t ntiles = (int64_t)((j.X + g.tx - 1) / g.tx) * ((j.Y + g.ty - 1) / g.ty);
+    // the output region's tiles and z extent (the whole volume unless a range)
+    const int RX = j.roi[3] - j.roi[0], RY = j.roi[4] - j.roi[1], RZ = j.roi[5] - j.roi[2];
+    const int64_t ntiles = (int64_t)((RX + g.tx - 1) / g.tx) * ((RY + g.ty - 1) / g.ty);
     // tz = 1 mod k: the slab's tz + k - 1 input planes are whole ring turns
     const void* fn = (const void*)&filter_dot4_kernel<K, SG>;
-    const int tz = plan_tz(ntiles, j.Z, K, g.tz_min, 128, resident_wgs(fn), K);
+    const int tz = plan_tz(ntiles, RZ, K, g.tz_min, 128, resident_wgs(fn), K);
     const VolDesc a = make_desc(j, tz, g);
-    const int64_t nb = ntiles * ((j.Z + tz - 1) / tz);
+    const int64_t nb = ntiles * ((RZ + tz - 1) / tz);
     if (nb > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL((filter_dot4_kernel<K, SG>), dim3((unsigned)nb), dim3(kNT), 0, s, a,
                        j.wq, (uint32_t)nb);

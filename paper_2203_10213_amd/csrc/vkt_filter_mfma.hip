@@ -309,8 +309,8 @@ __device__ void mfma_tile(const VolDesc& a, const float* __restrict__ w, int til
     const T* __restrict__ src = static_cast<const T*>(a.src);
 
     const int t = threadIdx.x, lane = t % 64, wave = t / 64;
-    const int x0 = (tile % a.tiles_x) * C::TX, y0 = (tile / a.tiles_x) * C::TY;
-    const int zb = slab * a.tz, ze = min(zb + a.tz, a.Z);
+    const int x0 = a.rx0 + (tile % a.tiles_x) * C::TX, y0 = a.ry0 + (tile / a.tiles_x) * C::TY;
+    const int zb = a.rz0 + slab * a.tz, ze = min(zb + a.tz, a.rz1);
     const int64_t plane = (int64_t)a.X * a.Y;
     const int32_t plane_bytes = (int32_t)(plane * (int64_t)sizeof(T));  // < 2^31 (host check)
 
@@ -382,8 +382,8 @@ __device__ void mfma_tile(const VolDesc& a, const float* __restrict__ w, int til
     const int xw = x0 + BX * wave, yl = y0 + lane;
     // rows past the volume's last row fall beyond the plane: dropped
     const uint32_t ooff =
-        yl < a.Y ? ((uint32_t)yl * (uint32_t)a.X + (uint32_t)xw) * (uint32_t)sizeof(T) : kOutside;
-    const bool vec_row = a.vec_ok && xw + BX <= a.X;
+        yl < a.ry1 ? ((uint32_t)yl * (uint32_t)a.X + (uint32_t)xw) * (uint32_t)sizeof(T) : kOutside;
+    const bool vec_row = a.vec_ok && xw + BX <= a.rx1;
 
     acc_t acc[C::MTW];
 #pragma unroll
@@ -478,7 +478,7 @@ __device__ void mfma_tile(const VolDesc& a, const float* __restrict__ w, int til
             const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(
                 static_cast<char*>(a.dst) + (int64_t)zo * plane_bytes, (short)0, plane_bytes,
                 (int)kRsrcWord3);
-            store_row<T, BX>(rd, ooff, v, vec_row, a.X - xw, a.unscale);
+            store_row<T, BX>(rd, ooff, v, vec_row, a.rx1 - xw, a.unscale);
             asm volatile("" ::: "memory");
         }
         // ---- advance the ring
@@ -561,13 +561,15 @@ template <class C>
 hipError_t launch_cfg(const FilterJob& j, hipStream_t s)
 {
     const ClassGeom g = geom_here(j.k);
-    const int64_t ntiles = (int64_t)((j.X + g.tx - 1) / g.tx) * ((j.Y + g.ty - 1) / g.ty);
+    // the output region's tiles and z extent (the whole volume unless a range)
+    const int RX = j.roi[3] - j.roi[0], RY = j.roi[4] - j.roi[1], RZ = j.roi[5] - j.roi[2];
+    const int64_t ntiles = (int64_t)((RX + g.tx - 1) / g.tx) * ((RY + g.ty - 1) / g.ty);
     const void* fn = (const void*)&filter_mfma_kernel<C>;
     // (deeper slabs measured slower for the 16x16 tiles, faster for 32x32)
-    const int tz = plan_tz(ntiles, j.Z, j.k, g.tz_min, C::SHAPE == 16 ? 128 : 512,
+    const int tz = plan_tz(ntiles, RZ, j.k, g.tz_min, C::SHAPE == 16 ? 128 : 512,
                            resident_wgs(fn), 1);
     const VolDesc a = make_desc(j, tz, g);
-    const int64_t nb = ntiles * ((j.Z + tz - 1) / tz);
+    const int64_t nb = ntiles * ((RZ + tz - 1) / tz);
     if (nb > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL((filter_mfma_kernel<C>), dim3((unsigned)nb), dim3(kNT), 0, s, a, j.wf,
                        (uint32_t)nb);

@@ -174,8 +174,8 @@ __device__ void valu_tile(const VolDesc& a, const typename AccT<IACC>::type* __r
     T* __restrict__ dst = static_cast<T*>(a.dst);
 
     const int t = threadIdx.x, tx = t % kBX, ty = t / kBX;
-    const int x0 = (tile % a.tiles_x) * kTX, y0 = (tile / a.tiles_x) * kTY;
-    const int zb = slab * a.tz, ze = min(zb + a.tz, a.Z);
+    const int x0 = a.rx0 + (tile % a.tiles_x) * kTX, y0 = a.ry0 + (tile / a.tiles_x) * kTY;
+    const int zb = a.rz0 + slab * a.tz, ze = min(zb + a.tz, a.rz1);
     const int64_t plane = (int64_t)a.X * a.Y;
 
     // Halo gather: the same (x, y) cells for every plane of the slab.
@@ -228,7 +228,7 @@ __device__ void valu_tile(const VolDesc& a, const typename AccT<IACC>::type* __r
     __syncthreads();
 
     const int ox = x0 + kVX * tx, oy = y0 + kVY * ty;
-    const bool vec = a.vec_ok && ox + kVX <= a.X;
+    const bool vec = a.vec_ok && ox + kVX <= a.rx1;
     for (int zi = zi_beg; zi < zi_end; ++zi) {
         const int cur = (zi - zi_beg) & 1;
         if (zi + 1 < zi_end) put(lds + (cur ^ 1) * G::LDS_CELLS);
@@ -310,7 +310,7 @@ __device__ void valu_tile(const VolDesc& a, const typename AccT<IACC>::type* __r
 #pragma unroll
             for (int vy = 0; vy < kVY; ++vy) {
                 const int y = oy + vy;
-                if (y >= a.Y) continue;
+                if (y >= a.ry1) continue;
                 T* o = orow + (int64_t)y * a.X + ox;
                 T r4[kVX];
 #pragma unroll
@@ -326,7 +326,7 @@ __device__ void valu_tile(const VolDesc& a, const typename AccT<IACC>::type* __r
                 } else {
 #pragma unroll
                     for (int vx = 0; vx < kVX; ++vx)
-                        if (ox + vx < a.X) o[vx] = r4[vx];
+                        if (ox + vx < a.rx1) o[vx] = r4[vx];
                 }
             }
         }
@@ -391,11 +391,13 @@ template <typename T, int K, bool IACC>
 hipError_t launch_k(const FilterJob& j, hipStream_t s)
 {
     const ClassGeom g = valu_geom(K);
-    const int64_t ntiles = (int64_t)((j.X + g.tx - 1) / g.tx) * ((j.Y + g.ty - 1) / g.ty);
+    // the output region's tiles and z extent (the whole volume unless a range)
+    const int RX = j.roi[3] - j.roi[0], RY = j.roi[4] - j.roi[1], RZ = j.roi[5] - j.roi[2];
+    const int64_t ntiles = (int64_t)((RX + g.tx - 1) / g.tx) * ((RY + g.ty - 1) / g.ty);
     const void* fn = (const void*)&filter_valu_kernel<T, K, IACC>;
-    const int tz = plan_tz(ntiles, j.Z, K, g.tz_min, 128, resident_wgs(fn), 1);
+    const int tz = plan_tz(ntiles, RZ, K, g.tz_min, 128, resident_wgs(fn), 1);
     const VolDesc a = make_desc(j, tz, g);
-    const int64_t nb = ntiles * ((j.Z + tz - 1) / tz);
+    const int64_t nb = ntiles * ((RZ + tz - 1) / tz);
     if (nb > 0x7fffffff) return hipErrorInvalidValue;
     using Acc = typename AccT<IACC>::type;
     const Acc* w;

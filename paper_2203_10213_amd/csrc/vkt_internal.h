@@ -79,6 +79,7 @@ struct FilterJob {
     float inv_D;             // 1/D for float outputs of integer filters
     bool vec_store;          // dst rows can take 16-B-aligned vector stores
     float wscale;            // 2^s with max|w| * 2^s in [2^14, 2^15) (fp16 splitting)
+    int32_t roi[6];          // output region [x0, y0, z0, x1, y1, z1)
     bool dot4;               // uint8 cells, 8-bit packed integer weights
     bool q_signed;           // signed 8-bit weights (cells enter as s - 128)
     const uint32_t* wq;      // device packed weights
@@ -112,6 +113,8 @@ struct VolDesc {
     int32_t vec_ok;
     float wscale, unscale;   // fp16 weight scaling of the matrix-core path
     float bias;              // dot-product path: 1/(4D) (+ 128 sum(w) / D)
+    int32_t rx0, ry0, rz0;   // output region: tiles start here ...
+    int32_t rx1, ry1, rz1;   // ... and outputs stop here (exclusive)
 };
 
 // One work item of a batched launch: a tile-slab of one volume.
@@ -183,9 +186,11 @@ int plan_tz(int64_t ntiles, int Z, int k, int tz_min, int tz_max, int slots, int
 
 // Validation and planning shared by the single and batched calls: fills j
 // and the chosen path (mfma, six products) for one (dst, src, filter) triple.
+// roi: output region [x0, y0, z0, x1, y1, z1), NULL for the whole volume
+// (validated by the caller).
 vktError build_job(const vktStructuredVolume_* dst, const vktStructuredVolume_* src,
                    const vktFilter_* filt, int mode, vktPrecision prec, FilterJob& j,
-                   bool& mfma, bool& six);
+                   bool& mfma, bool& six, const int32_t* roi = nullptr);
 bool live_volume(const vktStructuredVolume_* v);
 bool live_filter(const vktFilter_* f);
 vktError from_hip(hipError_t e);

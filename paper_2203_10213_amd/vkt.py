@@ -47,6 +47,7 @@ SIGNATURES = {
     "vktFillSV": [_P, _F],
     "vktFillRangeSV": [_P, _I32, _I32, _I32, _I32, _I32, _I32, _F],
     "vktApplyFilter": [_P, _P, _P, ctypes.c_int],
+    "vktApplyFilterRange": [_P, _P, _P, _I32, _I32, _I32, _I32, _I32, _I32, ctypes.c_int],
     "vktApplyFilterBatched": [_I32, _PP, _PP, _PP, ctypes.c_int],
     "vktSetAutotune": [ctypes.c_int],
     "vktSetStream": [_P],
@@ -195,6 +196,13 @@ def vktApplyFilter(dst, src, filt, mode=vktAddressModeClamp):
     _ok(lib().vktApplyFilter(dst, src, filt, m), "vktApplyFilter")
 
 
+def vktApplyFilterRange(dst, src, filt, first, last, mode=vktAddressModeClamp):
+    """first, last: (x, y, z) bounds of the half-open output region."""
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    _ok(lib().vktApplyFilterRange(dst, src, filt, *[int(v) for v in first],
+                                  *[int(v) for v in last], m), "vktApplyFilterRange")
+
+
 def vktApplyFilterBatched(dsts, srcs, filts, mode=vktAddressModeClamp):
     """dsts, srcs, filts: equal-length sequences of handles."""
     n = len(dsts)
@@ -253,15 +261,19 @@ def volume_from_tensor(t, lo=0.0, hi=1.0):
                                                   t.data_ptr(), lo, hi)
 
 
-def apply_filter(dst, src, weights, mode="clamp", divisor=None):
+def apply_filter(dst, src, weights, mode="clamp", divisor=None, roi=None):
     """One ApplyFilter of src into dst (device tensors) on torch's current
-    stream; integer weights with `divisor` create an integer filter."""
+    stream; integer weights with `divisor` create an integer filter; roi =
+    ((x0, y0, z0), (x1, y1, z1)) runs the range version."""
     vktSetStream(torch.cuda.current_stream())
     hs = volume_from_tensor(src)
     hd = volume_from_tensor(dst)
     hf = vktFilterCreate(weights) if divisor is None else vktFilterCreateInt(weights, divisor)
     try:
-        vktApplyFilter(hd, hs, hf, mode)
+        if roi is None:
+            vktApplyFilter(hd, hs, hf, mode)
+        else:
+            vktApplyFilterRange(hd, hs, hf, roi[0], roi[1], mode)
     finally:
         vktFilterDestroy(hf)
         vktStructuredVolumeDestroy(hd)

@@ -35,24 +35,32 @@ def sentinel_like(t):
 
 
 def run_filter(src_np, weights, mode="clamp", divisor=None, precision="auto",
-               src_t=None):
-    """ApplyFilter on the GPU through the C interface; returns numpy."""
+               src_t=None, roi=None):
+    """ApplyFilter (or its range version for roi = ((x0, y0, z0), (x1, y1,
+    z1))) on the GPU through the C interface into a sentinel-filled output;
+    returns numpy."""
     import torch
     from paper_2203_10213_amd import vkt
     src = to_device(src_np) if src_t is None else src_t
     dst = sentinel_like(src)
     vkt.vktSetPrecision(precision)
-    vkt.apply_filter(dst, src, weights, mode, divisor)
+    vkt.apply_filter(dst, src, weights, mode, divisor, roi=roi)
     vkt.vktSynchronize()
     torch.cuda.synchronize()
     return dst.cpu().numpy()
 
 
 def check_against_oracle(orc, src, w, mode, out, divisor=None, pts=None,
-                         tol=TOL_F32, what=""):
-    """Compare a GPU result with the oracle, on every cell or at pts."""
+                         tol=TOL_F32, what="", roi=None):
+    """Compare a GPU result with the oracle, on every cell, at pts, or on the
+    cells of roi = ((x0, y0, z0), (x1, y1, z1))."""
     wd = np.asarray(w, np.float64)
-    if pts is None:
+    if roi is not None:
+        (x0, y0, z0), (x1, y1, z1) = roi
+        T, A = orc.correlate(src, wd, mode, nthreads=ORACLE_THREADS)
+        sl = (slice(z0, z1), slice(y0, y1), slice(x0, x1))
+        T, A, got = T[sl], A[sl], out[sl]
+    elif pts is None:
         T, A = orc.correlate(src, wd, mode, nthreads=ORACLE_THREADS)
         got = out
     else:

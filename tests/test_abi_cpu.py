@@ -42,6 +42,7 @@ def test_error_strings(vkt):
 def test_null_handles_rejected_without_gpu(vkt):
     L = vkt.lib()
     assert L.vktApplyFilter(None, None, None, 0) == vkt.vktInvalidValue
+    assert L.vktApplyFilterRange(None, None, None, 0, 0, 0, 1, 1, 1, 0) == vkt.vktInvalidValue
     assert L.vktFill(None, 1.0) == vkt.vktInvalidValue
     assert L.vktFillRange(None, 0, 0, 0, 1, 1, 1, 1.0) == vkt.vktInvalidValue
     assert L.vktFilterDestroy(None) == vkt.vktInvalidValue
@@ -50,6 +51,7 @@ def test_null_handles_rejected_without_gpu(vkt):
     # a pointer that was never a handle is rejected, not dereferenced
     bogus = 0x1000
     assert L.vktApplyFilter(bogus, bogus, bogus, 0) == vkt.vktInvalidValue
+    assert L.vktApplyFilterRange(bogus, bogus, bogus, 0, 0, 0, 1, 1, 1, 0) == vkt.vktInvalidValue
     # bad k / NULL weights fail before any device allocation
     assert L.vktFilterCreate(None, 3, None) == vkt.vktInvalidValue
     assert L.vktStructuredVolumeCreate(None, 4, 4, 4, 0, 1, 1, 1, 0, 1) == vkt.vktInvalidValue
