@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample")
+    ap.add_argument("--separable", action="store_true",
+                    help="rank-1 fast path (vktSetSeparable): three 1-D passes for separable "
+                         "filters; reported apart from the dense numbers")
     ap.add_argument("--autotune", action="store_true",
                     help="c4: let the batched planner time its slab-depth candidates")
     ap.add_argument("--copy-probe", action="store_true",
@@ -131,26 +134,53 @@ def arith_dtype(c, precision):
         return "f16x2->f32"
     if c["path"] == "dot4":
         return "u8dot4->i32"
+    if c["path"] == "sep":
+        return "f32(rank-1)"
     if c["D"] is not None:
         return "f32(exact int)"
     return "f32"
 
 
-def kernel_path(c, precision):
+def kernel_path(c, precision, separable=False):
     """The library's plan rule: float-weight filters with k >= 5 run on the
     matrix cores unless the precision is fp32; uint8 volumes with integer
     filters of k <= 7, weights all in [0, 255] or all in [-128, 127],
     sum |w| <= 2048, divisor <= 2^19 and rows of a multiple of 4 cells run as
     8-bit dot products; the rest on the vector ALUs in FP32 / int32."""
     import numpy as np
+    if separable and rank1(c["w"]) and not (c["k"] <= 3 and dot4_ok(c)):
+        return "sep"
     if c["D"] is None:
         return "mfma" if (c["k"] >= 5 and precision != "fp32") else "valu"
+    return "dot4" if dot4_ok(c) else "valu"
+
+
+def dot4_ok(c):
+    """The 8-bit dot-product path's eligibility (uint8 cells, integer
+    filter, k <= 7, weights in [0, 255] or [-128, 127], sum |w| <= 2048,
+    divisor <= 2^19, rows of a multiple of 4 cells)."""
+    import numpy as np
+    if c["D"] is None:
+        return False
     w = np.asarray(c["w"], np.int64)
     fits = (w.min() >= 0 and w.max() <= 255) or (w.min() >= -128 and w.max() <= 127)
-    if (c["src"].dtype == torch_uint8() and c["k"] in (3, 5, 7) and fits
-            and np.abs(w).sum() <= 2048 and c["D"] <= (1 << 19) and c["src"].shape[-1] % 4 == 0):
-        return "dot4"
-    return "valu"
+    return bool(c["src"].dtype == torch_uint8() and c["k"] in (3, 5, 7) and fits
+                and np.abs(w).sum() <= 2048 and c["D"] <= (1 << 19)
+                and c["src"].shape[-1] % 4 == 0)
+
+
+def rank1(w):
+    """The library's rank-1 test (float filters to 2^-21 max|w|; the integer
+    filters of these workloads are exact outer products)."""
+    import numpy as np
+    w = np.asarray(w, np.float64)
+    k = w.shape[0]
+    ip = np.unravel_index(np.argmax(np.abs(w)), w.shape)
+    p = w[ip]
+    if p == 0:
+        return False
+    t, v, u = w[:, ip[1], ip[2]] / p, w[ip[0], :, ip[2]] / p, w[ip[0], ip[1], :]
+    return bool(np.max(np.abs(np.einsum("c,b,a->cba", t, v, u) - w)) <= np.ldexp(abs(p), -21))
 
 
 def torch_uint8():
@@ -165,7 +195,8 @@ def case_roofline(c, ms):
     cores (split products and Toeplitz zeros are overhead, not counted)."""
     t = ms * 1e-3
     bytes_alg = 2 * c["voxels"] * c["cell_bytes"]
-    flops = c["voxels"] * c["flops_per_voxel"]
+    # the rank-1 path's algorithm is three 1-D passes: 2 * 3k flops per output
+    flops = c["voxels"] * (6 * c["k"] if c.get("path") == "sep" else c["flops_per_voxel"])
     gbs = bytes_alg / t / 1e9
     tfs = flops / t / 1e12
     peak_c = {"mfma": BF16_MFMA_PEAK_TF, "dot4": INT8_DOT_PEAK_TOPS}.get(c["path"], FP32_VECTOR_PEAK_TF)
@@ -335,13 +366,14 @@ def main():
     stream = torch.cuda.current_stream()
     vkt.vktSetStream(stream)
     vkt.vktSetPrecision(args.precision)
+    vkt.vktSetSeparable(args.separable)
     if args.workload == "c4":
         print(json.dumps(run_batched(args, vkt, torch)))
         return
     print(f"[bench] building inputs for {args.workload}", file=sys.stderr, flush=True)
     cases = make_cases(args.workload, dev)
     for c in cases:
-        c["path"] = kernel_path(c, args.precision)
+        c["path"] = kernel_path(c, args.precision, args.separable)
         c["dst"] = torch.empty_like(c["src"])
         c["hs"] = vkt.volume_from_tensor(c["src"])
         c["hd"] = vkt.volume_from_tensor(c["dst"])
@@ -397,7 +429,8 @@ def main():
 
     dtype = {torch.uint8: "u8", torch.uint16: "u16", torch.float32: "f32"}
     line = {
-        "metric": "Gvoxels/s ApplyFilter on 1 MI355X",
+        "metric": ("Gvoxels/s ApplyFilter on 1 MI355X" +
+                   (" (rank-1 separable fast path)" if args.separable else "")),
         "value": value, "unit": "Gvoxels/s", "n_gpus": 1, "steps": K,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
@@ -407,7 +440,8 @@ def main():
                    "cases": [f"{c['name']} ({dtype[c['src'].dtype]} "
                              f"{'x'.join(str(v) for v in reversed(c['src'].shape))})"
                              for c in cases],
-                   "address_mode": "clamp", "precision": args.precision},
+                   "address_mode": "clamp", "precision": args.precision,
+                   "separable": bool(args.separable)},
         "roofline": roof,
         "cpu_baseline": cpu,
         "per_case": per_case,

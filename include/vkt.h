@@ -209,6 +209,21 @@ vktError vktGetPrecision(vktPrecision* precision);
  * the VKT_AUTOTUNE environment variable, "1" enables). */
 vktError vktSetAutotune(int enable);
 
+/* Rank-1 fast path (opt-in, per thread; default: the VKT_SEPARABLE
+ * environment variable, "1" enables).  A filter whose weights factor as
+ * w[c][b][a] = t[c] v[b] u[a] -- exactly for integer filters, to within
+ * 2^-21 max|w| for float filters -- then runs as three one-dimensional
+ * passes (3k instead of k^3 multiply-adds per cell, FP32 arithmetic), in
+ * vktApplyFilter and vktApplyFilterRange.  Integer filters on integer
+ * formats take it only while every partial sum stays an exact integer in
+ * FP32, so their results are unchanged; float results may differ from the
+ * dense sum by rounding (within the float tolerances).  The batched form
+ * always runs the dense arithmetic. */
+vktError vktSetSeparable(int enable);
+vktError vktGetSeparable(int* enable);
+/* *separable = 1 if the filter's weights are rank 1 (as above), else 0. */
+vktError vktFilterIsSeparable(vktFilter filter, int* separable);
+
 /* Wait for the calling thread's stream; reports faults of enqueued work. */
 vktError vktSynchronize(void);
 

@@ -4,6 +4,7 @@
 // The per-thread state mirrors the paper's thread-local ExecutionPolicy
 // (Sec. 3.1): the stream work is enqueued on and the arithmetic precision.
 // Volumes are device resident; there is no implicit host<->device migration.
+#include <climits>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -20,6 +21,7 @@ struct ThreadState {
     hipStream_t stream = nullptr;
     vktPrecision precision = vktPrecisionAuto;
     bool autotune = false;
+    bool separable = false;
     bool init = false;
 };
 thread_local ThreadState t_state;
@@ -34,6 +36,7 @@ ThreadState& state()
             else if (!std::strcmp(p, "splitbf16x6")) t_state.precision = vktPrecisionSplitBF16x6;
         }
         if (const char* p = std::getenv("VKT_AUTOTUNE")) t_state.autotune = p[0] == '1';
+        if (const char* p = std::getenv("VKT_SEPARABLE")) t_state.separable = p[0] == '1';
     }
     return t_state;
 }
@@ -104,6 +107,97 @@ vktError create_volume(vktStructuredVolume* out, int32_t dx, int32_t dy, int32_t
     return vktNoError;
 }
 
+// Rank-1 test of a k^3 filter (index a + k (b + k c)), pivot p at the
+// largest |w| (a*, b*, c*).  The rows through the pivot, w[c*][b*][:],
+// w[c*][:][a*] and w[:][b*][a*], are proportional to the factors.
+//  * Integer filters: each row divided by the gcd of its entries gives a
+//    primitive integer vector x, y, z (sign: positive at the pivot); then
+//    w = alpha x (x) y (x) z with alpha = p / (x[a*] y[b*] z[c*]) an integer,
+//    and u = alpha x, v = y, t = z reproduce w exactly (checked exactly, so
+//    sum|u| sum|v| sum|t| = sum|w|).
+//  * Float filters: u = w[c*][b*][:], v = w[c*][:][a*] / p,
+//    t = w[:][b*][a*] / p, accepted when every weight is reproduced to
+//    within 2^-21 max|w| (a few rounding steps of FP32 weights built as an
+//    outer product).
+struct Rank1 {
+    bool ok = false;
+    std::vector<double> u, v, t;
+};
+int64_t gcd64(int64_t a, int64_t b)
+{
+    a = a < 0 ? -a : a;
+    b = b < 0 ? -b : b;
+    while (b) {
+        const int64_t r = a % b;
+        a = b;
+        b = r;
+    }
+    return a;
+}
+Rank1 rank1(int k, const std::vector<double>& w, bool exact_int)
+{
+    Rank1 r;
+    const int n = k * k * k;
+    int ip = 0;
+    for (int i = 1; i < n; ++i)
+        if (std::fabs(w[i]) > std::fabs(w[ip])) ip = i;
+    const double p = w[ip];
+    if (p == 0.0) return r;
+    const int as = ip % k, bs = (ip / k) % k, cs = ip / (k * k);
+    auto at = [&](int a, int b, int c) { return w[a + k * (b + k * c)]; };
+    std::vector<double> ru(k), rv(k), rt(k);
+    for (int i = 0; i < k; ++i) {
+        ru[i] = at(i, bs, cs);
+        rv[i] = at(as, i, cs);
+        rt[i] = at(as, bs, i);
+    }
+    if (exact_int) {
+        std::vector<int64_t> x(k), y(k), z(k);
+        auto primitive = [&](const std::vector<double>& row, int piv, std::vector<int64_t>& out) {
+            int64_t g = 0;
+            for (int i = 0; i < k; ++i) g = gcd64(g, (int64_t)row[i]);
+            const int64_t s = row[piv] < 0 ? -g : g;
+            for (int i = 0; i < k; ++i) out[i] = (int64_t)row[i] / s;
+        };
+        primitive(ru, as, x);
+        primitive(rv, bs, y);
+        primitive(rt, cs, z);
+        const int64_t den = x[as] * y[bs] * z[cs];  // > 0, divides p for rank 1
+        if (den == 0 || (int64_t)p % den != 0) return r;
+        const int64_t alpha = (int64_t)p / den;
+        for (int c = 0; c < k; ++c)
+            for (int b = 0; b < k; ++b)
+                for (int a = 0; a < k; ++a) {
+                    const __int128 prod = (__int128)(alpha * x[a]) * y[b] * z[c];
+                    if (prod != (__int128)(int64_t)at(a, b, c)) return r;
+                }
+        r.u.resize(k);
+        r.v.resize(k);
+        r.t.resize(k);
+        for (int i = 0; i < k; ++i) {
+            r.u[i] = (double)(alpha * x[i]);
+            r.v[i] = (double)y[i];
+            r.t[i] = (double)z[i];
+        }
+    } else {
+        const double amax = std::fabs(p);
+        r.u = ru;
+        r.v = rv;
+        r.t = rt;
+        for (int i = 0; i < k; ++i) {
+            r.v[i] /= p;
+            r.t[i] /= p;
+        }
+        for (int c = 0; c < k; ++c)
+            for (int b = 0; b < k; ++b)
+                for (int a = 0; a < k; ++a)
+                    if (std::fabs(r.u[a] * r.v[b] * r.t[c] - at(a, b, c)) > std::ldexp(amax, -21))
+                        return r;
+    }
+    r.ok = true;
+    return r;
+}
+
 vktError create_filter(vktFilter* out, int32_t k, const float* wf, const int32_t* wi,
                        int32_t divisor)
 {
@@ -166,10 +260,37 @@ vktError create_filter(vktFilter* out, int32_t k, const float* wf, const int32_t
         if (e == hipSuccess)
             e = hipMemcpy(dwq, hq.data(), hq.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
     }
+    // rank-1 factors for the separable path
+    float* dsep = nullptr;
+    Rank1 r1;
+    int64_t sep_sum_abs = 0;
+    if (e == hipSuccess) {
+        std::vector<double> wd(n);
+        for (int i = 0; i < n; ++i) wd[i] = wi ? (double)hi[i] : (double)hf[i];
+        r1 = rank1(k, wd, wi != nullptr);
+    }
+    if (e == hipSuccess && r1.ok) {
+        std::vector<float> hs(3 * 16 + vkt::kWeightPad, 0.f);
+        double su = 0, sv = 0, st = 0;
+        for (int i = 0; i < k; ++i) {
+            hs[i] = (float)r1.u[i];
+            hs[16 + i] = (float)r1.v[i];
+            hs[32 + i] = (float)r1.t[i];
+            su += std::fabs(r1.u[i]);
+            sv += std::fabs(r1.v[i]);
+            st += std::fabs(r1.t[i]);
+        }
+        const double prod = su * sv * st;
+        sep_sum_abs = prod < 9.0e18 ? (int64_t)prod : INT64_MAX;
+        e = hipMalloc(&dsep, hs.size() * sizeof(float));
+        if (e == hipSuccess)
+            e = hipMemcpy(dsep, hs.data(), hs.size() * sizeof(float), hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) {
         if (dwf) (void)hipFree(dwf);
         if (dwi) (void)hipFree(dwi);
         if (dwq) (void)hipFree(dwq);
+        if (dsep) (void)hipFree(dsep);
         return from_hip(e);
     }
     // power-of-two weight scale for fp16 operand splitting
@@ -183,11 +304,12 @@ vktError create_filter(vktFilter* out, int32_t k, const float* wf, const int32_t
     }
     auto* f = new (std::nothrow) vktFilter_{k, wi != nullptr, wi ? divisor : 1, sum_abs,
                                             wscale, 0, dwf, dwi, dwq, q_ok, q_signed,
-                                            sum_int, device};
+                                            sum_int, r1.ok, sep_sum_abs, dsep, device};
     if (!f) {
         (void)hipFree(dwf);
         if (dwi) (void)hipFree(dwi);
         if (dwq) (void)hipFree(dwq);
+        if (dsep) (void)hipFree(dsep);
         return vktOutOfMemory;
     }
     {
@@ -225,6 +347,7 @@ vktError from_hip(hipError_t e)
 hipStream_t thread_stream() { return state().stream; }
 vktPrecision thread_precision() { return state().precision; }
 bool thread_autotune() { return state().autotune; }
+bool thread_separable() { return state().separable; }
 
 VolDesc make_desc(const FilterJob& j, int tz, ClassGeom g)
 {
@@ -259,7 +382,7 @@ VolDesc make_desc(const FilterJob& j, int tz, ClassGeom g)
 
 vktError build_job(const vktStructuredVolume_* dst, const vktStructuredVolume_* src,
                    const vktFilter_* filt, int mode, vktPrecision prec, FilterJob& j,
-                   bool& mfma, bool& six, const int32_t* roi)
+                   bool& mfma, bool& six, const int32_t* roi, bool allow_sep)
 {
     if (!live_volume(dst) || !live_volume(src) || !live_filter(filt)) return vktInvalidValue;
     if (mode < vktAddressModeClamp || mode > vktAddressModeBorder) return vktInvalidValue;
@@ -315,6 +438,27 @@ vktError build_job(const vktStructuredVolume_* dst, const vktStructuredVolume_* 
              reinterpret_cast<uintptr_t>(dst->dev) % 4 == 0;
     j.q_signed = filt->q_signed;
     j.wq = filt->d_wq;
+    // Rank-1 filters on the separable path when the thread asks for it.  For
+    // integer filters on integer cells the three passes must stay exact in
+    // FP32: every partial sum an integer below 2^24.
+    j.sep = false;
+    j.wsep = filt->d_sep;
+    if (allow_sep && state().separable && filt->sep_ok) {
+        if (!filt->is_int) {
+            j.sep = true;
+        } else {
+            const int64_t mx = src->fmt == vktDataFormatUInt8 ? 255 : 65535;
+            j.sep = src->fmt == vktDataFormatFloat32 ||
+                    filt->sep_sum_abs * mx < (int64_t(1) << 24);
+        }
+        // (k = 3 integer filters on uint8 stay on the 8-bit dot products:
+        // measured faster than the three passes there)
+        if (j.dot4 && filt->k <= 3) j.sep = false;
+        if (j.sep) {
+            mfma = false;
+            j.dot4 = false;
+        }
+    }
     if (j.dot4) {
         // floor(T/D + 1/2) as round-to-nearest(T * (1/D) + bias); signed
         // weights add the 128 * sum(w) the cells lost by entering as s - 128
@@ -475,7 +619,7 @@ vktError vktFilterDestroy(vktFilter f)
         if (!f || !g_filters.erase(f)) return vktInvalidValue;
     }
     hipError_t e = hipFree(f->d_wf);
-    for (void* p : {(void*)f->d_wi, (void*)f->d_wq}) {
+    for (void* p : {(void*)f->d_wi, (void*)f->d_wq, (void*)f->d_sep}) {
         if (!p) continue;
         hipError_t e2 = hipFree(p);
         if (e == hipSuccess) e = e2;
@@ -518,6 +662,7 @@ vktError vktApplyFilter(vktStructuredVolume dst, vktStructuredVolume src, vktFil
     bool mfma = false, six = false;
     const vktError e = vkt::build_job(dst, src, filt, mode, state().precision, j, mfma, six);
     if (e != vktNoError) return e;
+    if (j.sep) return from_hip(vkt::launch_filter_sep(j, state().stream));
     if (mfma) return from_hip(vkt::launch_filter_mfma(j, six, state().stream));
     if (j.dot4) return from_hip(vkt::launch_filter_dot4(j, state().stream));
     return from_hip(vkt::launch_filter_valu(j, state().stream));
@@ -537,9 +682,30 @@ vktError vktApplyFilterRange(vktStructuredVolume dst, vktStructuredVolume src, v
         vkt::build_job(dst, src, filt, mode, state().precision, j, mfma, six, roi);
     if (e != vktNoError) return e;
     if (x0 == x1 || y0 == y1 || z0 == z1) return vktNoError;  // empty region
+    if (j.sep) return from_hip(vkt::launch_filter_sep(j, state().stream));
     if (mfma) return from_hip(vkt::launch_filter_mfma(j, six, state().stream));
     if (j.dot4) return from_hip(vkt::launch_filter_dot4(j, state().stream));
     return from_hip(vkt::launch_filter_valu(j, state().stream));
+}
+
+vktError vktSetSeparable(int enable)
+{
+    state().separable = enable != 0;
+    return vktNoError;
+}
+
+vktError vktGetSeparable(int* enable)
+{
+    if (!enable) return vktInvalidValue;
+    *enable = state().separable ? 1 : 0;
+    return vktNoError;
+}
+
+vktError vktFilterIsSeparable(vktFilter filter, int* separable)
+{
+    if (!separable || !vkt::live_filter(filter)) return vktInvalidValue;
+    *separable = filter->sep_ok ? 1 : 0;
+    return vktNoError;
 }
 
 vktError vktSetAutotune(int enable)

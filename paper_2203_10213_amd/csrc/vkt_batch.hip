@@ -431,7 +431,9 @@ vktError vktApplyFilterBatched(int32_t n, const vktStructuredVolume* dst,
     sig.push_back((uintptr_t)stream);
     for (int i = 0; i < n; ++i) {
         bool mfma = false, six = false;
-        const vktError e = build_job(dst[i], src[i], filters[i], mode, prec, tr[i].j, mfma, six);
+        // (the batched form always runs the dense arithmetic)
+        const vktError e =
+            build_job(dst[i], src[i], filters[i], mode, prec, tr[i].j, mfma, six, nullptr, false);
         if (e != vktNoError) return e;
         const FilterJob& j = tr[i].j;
         tr[i].f = filters[i];

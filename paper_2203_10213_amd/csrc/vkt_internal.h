@@ -34,6 +34,11 @@ struct vktFilter_ {
     uint32_t* d_wq;
     bool q_ok, q_signed;
     int64_t sum_int;            // sum w for integer filters
+    // rank-1 factors (u over x | v over y | t over z, 16 floats each) with
+    // u (x) v (x) t = w (exactly, with integer factors, for integer filters)
+    bool sep_ok;
+    int64_t sep_sum_abs;        // sum|u| sum|v| sum|t|
+    float* d_sep;
     int device;
 };
 
@@ -84,6 +89,8 @@ struct FilterJob {
     bool q_signed;           // signed 8-bit weights (cells enter as s - 128)
     const uint32_t* wq;      // device packed weights
     float q_bias;            // epilogue constant of the dot-product path
+    bool sep;                // rank-1 filter on the separable path
+    const float* wsep;       // device factors u | v | t (16 floats each)
 };
 
 // Stored-result rule of an ApplyFilter.
@@ -147,6 +154,8 @@ hipError_t launch_fill_range(void* dst, int cell_bytes, int32_t X, int32_t Y,
                              const int32_t first[3], const int32_t last[3],
                              uint32_t raw_bits, hipStream_t s);
 hipError_t launch_filter_valu(const FilterJob& j, hipStream_t s);
+// Rank-1 filters as three one-dimensional passes (opt-in, vktSetSeparable).
+hipError_t launch_filter_sep(const FilterJob& j, hipStream_t s);
 // 8-bit dot-product path for uint8 volumes with small integer filters.
 hipError_t launch_filter_dot4(const FilterJob& j, hipStream_t s);
 const void* dot4_batched_kernel(int k, bool q_signed);
@@ -187,15 +196,17 @@ int plan_tz(int64_t ntiles, int Z, int k, int tz_min, int tz_max, int slots, int
 // Validation and planning shared by the single and batched calls: fills j
 // and the chosen path (mfma, six products) for one (dst, src, filter) triple.
 // roi: output region [x0, y0, z0, x1, y1, z1), NULL for the whole volume
-// (validated by the caller).
+// (validated by the caller); allow_sep: the call has a separable kernel.
 vktError build_job(const vktStructuredVolume_* dst, const vktStructuredVolume_* src,
                    const vktFilter_* filt, int mode, vktPrecision prec, FilterJob& j,
-                   bool& mfma, bool& six, const int32_t* roi = nullptr);
+                   bool& mfma, bool& six, const int32_t* roi = nullptr,
+                   bool allow_sep = true);
 bool live_volume(const vktStructuredVolume_* v);
 bool live_filter(const vktFilter_* f);
 vktError from_hip(hipError_t e);
 hipStream_t thread_stream();
 vktPrecision thread_precision();
 bool thread_autotune();
+bool thread_separable();
 
 }  // namespace vkt

@@ -50,6 +50,9 @@ SIGNATURES = {
     "vktApplyFilterRange": [_P, _P, _P, _I32, _I32, _I32, _I32, _I32, _I32, ctypes.c_int],
     "vktApplyFilterBatched": [_I32, _PP, _PP, _PP, ctypes.c_int],
     "vktSetAutotune": [ctypes.c_int],
+    "vktSetSeparable": [ctypes.c_int],
+    "vktGetSeparable": [ctypes.POINTER(ctypes.c_int)],
+    "vktFilterIsSeparable": [_P, ctypes.POINTER(ctypes.c_int)],
     "vktSetStream": [_P],
     "vktGetStream": [_PP],
     "vktSetPrecision": [ctypes.c_int],
@@ -242,6 +245,22 @@ def vktGetPrecision():
 
 def vktSetAutotune(enable):
     _ok(lib().vktSetAutotune(1 if enable else 0), "vktSetAutotune")
+
+
+def vktSetSeparable(enable):
+    _ok(lib().vktSetSeparable(1 if enable else 0), "vktSetSeparable")
+
+
+def vktGetSeparable():
+    v = ctypes.c_int()
+    _ok(lib().vktGetSeparable(ctypes.byref(v)), "vktGetSeparable")
+    return bool(v.value)
+
+
+def vktFilterIsSeparable(filt):
+    v = ctypes.c_int()
+    _ok(lib().vktFilterIsSeparable(filt, ctypes.byref(v)), "vktFilterIsSeparable")
+    return bool(v.value)
 
 
 def vktSynchronize():

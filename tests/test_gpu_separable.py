@@ -1,0 +1,123 @@
+"""GPU checks of the rank-1 (separable) fast path: detection of rank-1
+filters, and with vktSetSeparable(1) results equal to the oracle's dense
+correlation at the ApplyFilter tolerances (bit-exact for integer filters on
+integer formats), for whole volumes and ranges; filters that are not rank 1
+still run the dense arithmetic."""
+import numpy as np
+import pytest
+
+from _gpu import check_against_oracle, run_filter
+
+pytestmark = pytest.mark.gpu
+
+MODES = ["clamp", "wrap", "mirror", "border"]
+
+
+@pytest.fixture(autouse=True)
+def _separable_on():
+    from paper_2203_10213_amd import vkt
+    vkt.vktSetSeparable(True)
+    yield
+    vkt.vktSetSeparable(False)
+
+
+def _outer(u, v, t):
+    return np.einsum("c,b,a->cba", np.asarray(t), np.asarray(v), np.asarray(u))
+
+
+def _is_sep(w, divisor=None):
+    from paper_2203_10213_amd import vkt
+    f = vkt.vktFilterCreate(w) if divisor is None else vkt.vktFilterCreateInt(w, divisor)
+    try:
+        return vkt.vktFilterIsSeparable(f)
+    finally:
+        vkt.vktFilterDestroy(f)
+
+
+def test_detection():
+    from paper_2203_10213_amd import synth
+    g = np.random.default_rng(5)
+    assert _is_sep(synth.gaussian_weights(5, 1.5))
+    assert _is_sep(synth.gaussian_weights(11, 2.5))
+    assert _is_sep(np.ones((3, 3, 3), np.int32), 27)
+    b = np.array([1, 2, 1])
+    assert _is_sep(_outer(b, b, b).astype(np.int32), 64)
+    assert _is_sep(_outer([1, 0, -1], b, b).astype(np.int32), 1)        # Sobel x
+    assert _is_sep(_outer([3, -1, 2, 5, 7], [2, 1, 1, 1, 4], [1, -6, 2, 2, 1]).astype(np.int32), 9)
+    assert not _is_sep(g.standard_normal((5, 5, 5)).astype(np.float32))
+    w = synth.gaussian_weights(5, 1.5).copy()
+    w[0, 1, 2] *= 1.001                      # a relative change far above rounding
+    assert not _is_sep(w)
+    wi = _outer(b, b, b).astype(np.int32)
+    wi[1, 1, 1] += 1
+    assert not _is_sep(wi, 64)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("dtype", [np.float32, np.uint16, np.uint8])
+def test_gaussians_match_dense_oracle(orc, mode, dtype):
+    from paper_2203_10213_amd import synth
+    g = np.random.default_rng(600 + MODES.index(mode))
+    for k, shape in [(3, (9, 33, 65)), (5, (12, 40, 70)), (7, (10, 35, 66)), (9, (11, 20, 40)),
+                     (11, (13, 34, 70)), (13, (6, 17, 30)), (15, (17, 40, 67)), (1, (3, 4, 5))]:
+        if dtype == np.float32:
+            src = g.standard_normal(shape).astype(np.float32)
+        else:
+            src = g.integers(0, np.iinfo(dtype).max + 1, shape).astype(dtype)
+        w = synth.gaussian_weights(k, k / 4)
+        out = run_filter(src, w, mode)
+        check_against_oracle(orc, src, w, mode, out, what=f"sep {dtype.__name__} k={k}")
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_integer_rank1_bit_exact(orc, mode):
+    g = np.random.default_rng(650 + MODES.index(mode))
+    b = np.array([1, 2, 1])
+    cases = [(np.uint8, np.ones((3, 3, 3), np.int32), 27, (20, 40, 130)),
+             (np.uint16, _outer(b, b, b).astype(np.int32), 64, (9, 33, 65)),
+             (np.uint8, _outer([1, 4, 6, 4, 1], [1, 4, 6, 4, 1], [1, 4, 6, 4, 1]).astype(np.int32),
+              4096, (8, 30, 41)),
+             (np.uint8, _outer([1, 0, -1], b, b).astype(np.int32), 3, (7, 19, 33)),
+             (np.float32, _outer([1, 0, -1], b, b).astype(np.int32), 1, (7, 19, 33)),
+             (np.uint16, _outer([3, -1, 2], [2, 1, 1], [1, -6, 2]).astype(np.int32), 7, (5, 21, 40))]
+    for dtype, w, D, shape in cases:
+        if dtype == np.float32:
+            src = g.standard_normal(shape).astype(np.float32)
+        else:
+            src = g.integers(0, np.iinfo(dtype).max + 1, shape).astype(dtype)
+        out = run_filter(src, w, mode, divisor=D)
+        check_against_oracle(orc, src, w, mode, out, divisor=D,
+                             what=f"sep int {dtype.__name__} k={w.shape[0]} D={D}")
+
+
+def test_not_rank1_runs_dense_arithmetic(orc):
+    """With the switch on, a filter that is not rank 1 gives the same bytes
+    as with the switch off."""
+    from paper_2203_10213_amd import vkt
+    g = np.random.default_rng(660)
+    src = g.standard_normal((10, 33, 64)).astype(np.float32)
+    w = g.standard_normal((5, 5, 5)).astype(np.float32)
+    on = run_filter(src, w, "clamp", precision="fp32")
+    vkt.vktSetSeparable(False)
+    off = run_filter(src, w, "clamp", precision="fp32")
+    assert np.array_equal(on.view(np.uint32), off.view(np.uint32))
+
+
+def test_separable_range(orc):
+    from paper_2203_10213_amd import synth
+    g = np.random.default_rng(670)
+    src = g.integers(0, 65536, (14, 40, 70)).astype(np.uint16)
+    w = synth.gaussian_weights(7, 1.75)
+    for roi in [((3, 5, 2), (60, 33, 11)), ((0, 0, 0), (70, 40, 14)), ((69, 39, 13), (70, 40, 14))]:
+        out = run_filter(src, w, "mirror", roi=roi)
+        check_against_oracle(orc, src, w, "mirror", out, roi=roi, what=f"sep range {roi}")
+
+
+def test_switch_is_thread_local():
+    import threading
+    from paper_2203_10213_amd import vkt
+    seen = []
+    th = threading.Thread(target=lambda: seen.append(vkt.vktGetSeparable()))
+    th.start()
+    th.join()
+    assert vkt.vktGetSeparable() is True and seen == [False]
