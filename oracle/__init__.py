@@ -48,9 +48,12 @@ def lib():
                                 ctypes.c_double, ctypes.c_int, dp]
     L.vkto_fill_range.argtypes = [vp, ctypes.c_int, i64, i64, i64, i64, i64,
                                   i64, i64, i64, i64, ctypes.c_double]
+    L.vkto_resample_linear.argtypes = [vp, ctypes.c_int, i64, i64, i64, i64, i64, i64,
+                                       dp, dp]
+    L.vkto_flip.argtypes = [vp, ctypes.c_int, i64, i64, i64, ctypes.c_int, vp]
     for f in ("vkto_correlate", "vkto_correlate_points",
               "vkto_store_float_filter", "vkto_store_int_filter",
-              "vkto_fill_raw", "vkto_fill_range"):
+              "vkto_fill_raw", "vkto_fill_range", "vkto_resample_linear", "vkto_flip"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -165,3 +168,26 @@ def fill_range(vol, first, last, raw):
                                  *[int(v) for v in last], float(raw)),
            "fill_range")
     return vol
+
+
+def resample(src, dims):
+    """Trilinear cell-centred resampling of src (Z, Y, X) to dims = (X, Y, Z)
+    (paper Sec. 3.2 Resample); returns (values, sum of |w s|) in FP64."""
+    src = _volume(src)
+    Xo, Yo, Zo = (int(d) for d in dims)
+    Z, Y, X = src.shape
+    out = np.empty((Zo, Yo, Xo), np.float64)
+    A = np.empty_like(out)
+    _check(lib().vkto_resample_linear(src.ctypes.data, _FMT[src.dtype], X, Y, Z, Xo, Yo, Zo,
+                                      _dp(out), _dp(A)), "vkto_resample_linear")
+    return out, A
+
+
+def flip(src, axis):
+    """src mirrored along axis 0 = x, 1 = y, 2 = z (paper Sec. 3.2 Flip)."""
+    src = _volume(src)
+    Z, Y, X = src.shape
+    out = np.empty_like(src)
+    _check(lib().vkto_flip(src.ctypes.data, _FMT[src.dtype], X, Y, Z, int(axis),
+                           out.ctypes.data), "vkto_flip")
+    return out

@@ -268,3 +268,78 @@ int vkto_fill_range(void* dst, int fmt, int64_t X, int64_t Y, int64_t Z,
             }
     return 0;
 }
+
+/* ---- Resample: trilinear, cell-centred, clamp to the volume (Sec. 3.2) --- */
+
+/* Lower neighbour index and weight of the upper one for destination cell i
+ * on an axis of n source and m destination cells. */
+static void lin_axis(int64_t i, int64_t n, int64_t m, int64_t* i0, int64_t* i1, double* f)
+{
+    const double u = ((double)i + 0.5) * (double)n / (double)m - 0.5;
+    const double fl = floor(u);
+    int64_t a = (int64_t)fl, b = a + 1;
+    *f = u - fl;
+    if (a < 0) a = 0;
+    if (a > n - 1) a = n - 1;
+    if (b < 0) b = 0;
+    if (b > n - 1) b = n - 1;
+    *i0 = a;
+    *i1 = b;
+}
+
+int vkto_resample_linear(const void* src, int fmt, int64_t X, int64_t Y, int64_t Z,
+                         int64_t Xo, int64_t Yo, int64_t Zo, double* out, double* Aabs)
+{
+    if (!src || !out || !valid_fmt(fmt) || X < 1 || Y < 1 || Z < 1 || Xo < 1 || Yo < 1 ||
+        Zo < 1)
+        return -1;
+    for (int64_t z = 0; z < Zo; ++z) {
+        int64_t z0, z1;
+        double fz;
+        lin_axis(z, Z, Zo, &z0, &z1, &fz);
+        for (int64_t y = 0; y < Yo; ++y) {
+            int64_t y0, y1;
+            double fy;
+            lin_axis(y, Y, Yo, &y0, &y1, &fy);
+            for (int64_t x = 0; x < Xo; ++x) {
+                int64_t x0, x1;
+                double fx;
+                lin_axis(x, X, Xo, &x0, &x1, &fx);
+                const int64_t xs[2] = {x0, x1}, ys[2] = {y0, y1}, zs[2] = {z0, z1};
+                const double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy}, wz[2] = {1.0 - fz, fz};
+                double s = 0.0, sa = 0.0;
+                for (int c = 0; c < 2; ++c)
+                    for (int b = 0; b < 2; ++b)
+                        for (int a = 0; a < 2; ++a) {
+                            const double w = wx[a] * wy[b] * wz[c];
+                            const double v = load_cell(src, fmt, xs[a] + X * (ys[b] + Y * zs[c]));
+                            s += w * v;
+                            sa += fabs(w * v);
+                        }
+                const int64_t o = x + Xo * (y + Yo * z);
+                out[o] = s;
+                if (Aabs) Aabs[o] = sa;
+            }
+        }
+    }
+    return 0;
+}
+
+/* ---- Flip along one axis (Sec. 3.2 transform algorithms) ----------------- */
+
+int vkto_flip(const void* src, int fmt, int64_t X, int64_t Y, int64_t Z, int axis, void* dst)
+{
+    if (!src || !dst || !valid_fmt(fmt) || X < 1 || Y < 1 || Z < 1 || axis < 0 || axis > 2)
+        return -1;
+    const size_t cb = fmt == VKTO_U8 ? 1 : fmt == VKTO_U16 ? 2 : fmt == VKTO_F32 ? 4 : 8;
+    for (int64_t z = 0; z < Z; ++z)
+        for (int64_t y = 0; y < Y; ++y)
+            for (int64_t x = 0; x < X; ++x) {
+                const int64_t sx = axis == 0 ? X - 1 - x : x;
+                const int64_t sy = axis == 1 ? Y - 1 - y : y;
+                const int64_t sz = axis == 2 ? Z - 1 - z : z;
+                memcpy((char*)dst + (x + X * (y + Y * z)) * cb,
+                       (const char*)src + (sx + X * (sy + Y * sz)) * cb, cb);
+            }
+    return 0;
+}

@@ -17,6 +17,8 @@
  *   Fill / FillRange -- paper Sec. 3.2 "Volume Manipulation" and Fig. 4: set
  *     every cell, or every cell of an axis-aligned region of interest given in
  *     cell coordinates, to one value mapped through the volume's value range.
+ *   Resample, Flip -- paper Sec. 3.2 (core and transform algorithms) and the
+ *     structured-volume benchmarks of Sec. 4.
  *
  * Layout: a volume of dims X*Y*Z is a dense array, x fastest:
  *   index(x, y, z) = x + X*(y + Y*z).
@@ -76,6 +78,24 @@ int vkto_fill_raw(double value, double lo, double hi, int fmt, double* raw);
 int vkto_fill_range(void* dst, int fmt, int64_t X, int64_t Y, int64_t Z,
                     int64_t x0, int64_t y0, int64_t z0, int64_t x1, int64_t y1,
                     int64_t z1, double raw);
+
+/* Resample (paper Sec. 3.2: a core algorithm that changes the size of a
+ * volume; benchmarked in Sec. 4 as a downscale by two on every axis).  out
+ * (Xo*Yo*Zo doubles, x fastest) receives, for every destination cell, the
+ * trilinear interpolation of src at the cell's centre mapped to source cell
+ * coordinates, u = (i + 1/2) * n_src / n_dst - 1/2 per axis, neighbours
+ * clamped to the volume (for a factor of exactly two: the mean of the
+ * 2 x 2 x 2 source block).  Aabs (may be NULL) receives the same
+ * interpolation of |src|. */
+int vkto_resample_linear(const void* src, int fmt, int64_t X, int64_t Y, int64_t Z,
+                         int64_t Xo, int64_t Yo, int64_t Zo, double* out, double* Aabs);
+
+/* Flip (paper Sec. 3.2, a transform algorithm; benchmarked in Sec. 4 along
+ * the axis of the longest extent): dst(x) = src(n - 1 - x) along axis
+ * (0 = x, 1 = y, 2 = z), every other coordinate unchanged.  dst and src are
+ * typed by fmt and must not overlap. */
+int vkto_flip(const void* src, int fmt, int64_t X, int64_t Y, int64_t Z, int axis,
+              void* dst);
 
 #ifdef __cplusplus
 }
