@@ -9,8 +9,11 @@ One step = one ApplyFilter of (a) and one of (b), with inputs resident in HBM.
 Prints ONE JSON line (metric Gvoxels/s = output cells / device time).
 
 Other workloads (--workload): c1 (64^3 float32, 3^3 Gaussian), c3a / c3b
-(1024^3 float32 blob field, dense 7^3 / 9^3 unit-L1 weights), c5 (2048 x 2048
-x 1024 uint16 ellipsoid phantom, 11^3 Gaussian sigma 2.5).
+(1024^3 float32 blob field, dense 7^3 / 9^3 unit-L1 weights), c4 (256 uneven
+uint16 volumes, batched), c5 (2048 x 2048 x 1024 uint16 ellipsoid phantom,
+11^3 Gaussian sigma 2.5), transforms (the two 512^3 volumes of the default
+workload: Resample down by two on every axis and Flip along the longest
+axis, the paper's other structured-volume benchmarks).
 """
 import argparse
 import hashlib
@@ -36,7 +39,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2",
-                    choices=["c1", "c2", "c2a", "c2b", "c3a", "c3b", "c4", "c5"])
+                    choices=["c1", "c2", "c2a", "c2b", "c3a", "c3b", "c4", "c5",
+                             "transforms"])
     ap.add_argument("--precision", default=None,
                     choices=["auto", "fp32", "splitbf16", "splitbf16x6"],
                     help="default: fp32 for c1/c2 (the plain-path configurations), "
@@ -342,6 +346,104 @@ def run_batched(args, vkt, torch):
     return line
 
 
+def run_transforms(args, vkt, torch):
+    """Resample by one half on every axis and Flip along the longest axis
+    (x for these cubes: the first of the equal extents) of the 512^3 uint8
+    phantom and the 512^3 float32 noise field; one step = the four calls.
+    Value: source voxels per second over the step.  Flips along y and z are
+    timed apart (per_case)."""
+    import numpy as np
+    from paper_2203_10213_amd import synth
+    S = synth.SEEDS
+    vols = [("u8_512_phantom", torch.from_numpy(synth.ct_phantom_u8(512, S["c2a"])).cuda()),
+            ("f32_512_noise", synth.smoothed_noise_f32(512, 4.0, S["c2b"], device="cuda"))]
+    stream = torch.cuda.current_stream()
+    ops, handles = [], []
+    for name, src in vols:
+        Z, Y, X = src.shape
+        half = torch.empty((Z // 2, Y // 2, X // 2), dtype=src.dtype, device=src.device)
+        flipped = torch.empty_like(src)
+        hs, hh, hf = (vkt.volume_from_tensor(t) for t in (src, half, flipped))
+        handles += [hs, hh, hf]
+        n, cb = src.numel(), src.element_size()
+        longest = int(np.argmax([X, Y, Z]))
+        ops.append(dict(case=f"resample_half_{name}", fn=lambda hh=hh, hs=hs: vkt.vktResample(hh, hs),
+                        voxels=n, bytes=n * cb + half.numel() * cb, step=True))
+        for ax in (longest,) + tuple(a for a in range(3) if a != longest):
+            ops.append(dict(case=f"flip_{'xyz'[ax]}_{name}",
+                            fn=lambda hf=hf, hs=hs, ax=ax: vkt.vktFlip(hf, hs, ax),
+                            voxels=n, bytes=2 * n * cb, step=ax == longest))
+    torch.cuda.synchronize()
+
+    def timed(op_list, K, W):
+        for _ in range(W):
+            for o in op_list:
+                o["fn"]()
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2 * len(op_list))]
+               for _ in range(K)]
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for s in range(K):
+            for i, o in enumerate(op_list):
+                evs[s][2 * i].record(stream)
+                o["fn"]()
+                evs[s][2 * i + 1].record(stream)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        vkt.vktSynchronize()
+        per = [sum(evs[s][2 * i].elapsed_time(evs[s][2 * i + 1]) for s in range(K)) / K
+               for i in range(len(op_list))]
+        return t0.elapsed_time(t1) / K, per
+
+    step_ops = [o for o in ops if o["step"]]
+    print(f"[bench] transforms, warmup {args.warmup}", file=sys.stderr, flush=True)
+    ms_step, per = timed(step_ops, args.steps, args.warmup)
+    extra = [o for o in ops if not o["step"]]
+    _, per_extra = timed(extra, max(1, args.steps // 2), 1)
+    per_case = []
+    for o, ms in list(zip(step_ops, per)) + list(zip(extra, per_extra)):
+        gbs = o["bytes"] / (ms * 1e-3) / 1e9
+        per_case.append(dict(case=o["case"], ms=ms, in_step=o["step"],
+                             gvoxels_s=o["voxels"] / (ms * 1e-3) / 1e9, hbm_gbs=gbs,
+                             hbm_frac=gbs / HBM_PEAK_GBS, algorithmic_bytes=o["bytes"]))
+    dom = max((p for p in per_case if p["in_step"]), key=lambda p: p["ms"])
+    roof = {"bound": "hbm", "achieved": dom["hbm_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": dom["hbm_frac"], "traffic": None, "kernel_case": dom["case"]}
+    voxels = sum(o["voxels"] for o in step_ops)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        print("[bench] timing the CPU oracle baseline", file=sys.stderr, flush=True)
+        t_cpu = 0.0
+        for name, src in vols:
+            h = src.cpu().numpy()
+            Z, Y, X = h.shape
+            t0 = time.perf_counter()
+            oracle.resample(h, (X // 2, Y // 2, Z // 2))
+            oracle.flip(h, int(np.argmax([X, Y, Z])))
+            t_cpu += time.perf_counter() - t0
+        cpu = {"value": voxels / t_cpu / 1e9, "unit": "Gvoxels/s", "cores": 1, "kind": "oracle",
+               "sample": "the oracle's resample (FP64) and flip of both whole 512^3 volumes, "
+                         "one thread"}
+    line = {
+        "metric": "Gvoxels/s Resample(1/2) + Flip(longest axis) on 1 MI355X",
+        "value": voxels / (ms_step * 1e-3) / 1e9, "unit": "Gvoxels/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u8+f32", "data": "synthetic",
+        "config": {"workload": "transforms",
+                   "cases": ["resample 512^3 -> 256^3 and flip along x of the u8 CT-like "
+                             "phantom and the f32 smoothed-noise field"]},
+        "roofline": roof, "cpu_baseline": cpu, "per_case": per_case,
+    }
+    for h in handles:
+        vkt.vktStructuredVolumeDestroy(h)
+    return line
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -369,6 +471,9 @@ def main():
     vkt.vktSetSeparable(args.separable)
     if args.workload == "c4":
         print(json.dumps(run_batched(args, vkt, torch)))
+        return
+    if args.workload == "transforms":
+        print(json.dumps(run_transforms(args, vkt, torch)))
         return
     print(f"[bench] building inputs for {args.workload}", file=sys.stderr, flush=True)
     cases = make_cases(args.workload, dev)

@@ -67,6 +67,13 @@ typedef enum vktPrecision {
     vktPrecisionSplitBF16x6 = 3  /* matrix cores, 6 bf16 products for Float32 */
 } vktPrecision;
 
+/* Axis of a volume: x (fastest in memory), y, z. */
+typedef enum vktAxis {
+    vktAxisX = 0,
+    vktAxisY = 1,
+    vktAxisZ = 2
+} vktAxis;
+
 typedef struct vktStructuredVolume_* vktStructuredVolume;
 typedef struct vktFilter_* vktFilter;
 
@@ -197,6 +204,34 @@ vktError vktApplyFilterRange(vktStructuredVolume dst, vktStructuredVolume src,
 vktError vktApplyFilterBatched(int32_t n, const vktStructuredVolume* dst,
                                const vktStructuredVolume* src,
                                const vktFilter* filters, vktAddressMode mode);
+
+/* ---- Resample and Flip (paper Sec. 3.2 core and transform algorithms;
+ *      Sec. 4 downscales by two and flips along the longest axis) --------- */
+
+/* Resample src onto dst's grid (any dims, same format): dst cell i on an
+ * axis of n source and m destination cells takes the source at the cell
+ * centre u = (i + 1/2) n / m - 1/2, trilinear between the neighbouring
+ * cells, neighbours clamped to the volume (so u outside [0, n - 1] takes the
+ * edge cell).  Stored as the FP32 value (Float32) or rounded half-up and
+ * saturated (UInt8/UInt16).  When every src dim is twice the dst dim the
+ * result is the mean of each 2x2x2 block, exact for integer formats
+ * ((sum + 4) / 8, truncated).  Other sizes interpolate in FP32 with
+ * positions formed in FP64: Float32 within a few FP32 roundings of the
+ * largest neighbour, integer formats within 1 of the exact rounding.
+ * Errors: vktInvalidValue for bad handles, different formats or overlapping
+ * buffers. */
+vktError vktResample(vktStructuredVolume dst, vktStructuredVolume src);
+
+/* dst = src mirrored along `axis`: dst(x) = src(n - 1 - x) on that axis.
+ * dst == src (the same buffer) flips in place; otherwise the buffers must not
+ * overlap.  Bit-exact for every format.
+ * Errors: vktInvalidValue for bad handles, an axis out of range, different
+ * dims or formats, or partly overlapping buffers. */
+vktError vktFlip(vktStructuredVolume dst, vktStructuredVolume src, vktAxis axis);
+
+/* The paper's C99 names; identical to vktResample / vktFlip. */
+vktError vktResampleSV(vktStructuredVolume dst, vktStructuredVolume src);
+vktError vktFlipSV(vktStructuredVolume dst, vktStructuredVolume src, vktAxis axis);
 
 /* ---- per-thread execution state (paper Sec. 3.1 ExecutionPolicy) -------- */
 

@@ -688,6 +688,42 @@ vktError vktApplyFilterRange(vktStructuredVolume dst, vktStructuredVolume src, v
     return from_hip(vkt::launch_filter_valu(j, state().stream));
 }
 
+vktError vktResample(vktStructuredVolume dst, vktStructuredVolume src)
+{
+    if (!live_volume(dst) || !live_volume(src) || dst->fmt != src->fmt) return vktInvalidValue;
+    const int64_t sb = cells(src) * vkt::cell_bytes(src->fmt);
+    const int64_t db = cells(dst) * vkt::cell_bytes(dst->fmt);
+    const char* d0 = static_cast<const char*>(dst->dev);
+    const char* s0 = static_cast<const char*>(src->dev);
+    if (d0 < s0 + sb && s0 < d0 + db) return vktInvalidValue;  // overlap
+    return from_hip(vkt::launch_resample(src->dev, dst->dev, src->fmt, src->dims, dst->dims,
+                                         state().stream));
+}
+
+vktError vktFlip(vktStructuredVolume dst, vktStructuredVolume src, vktAxis axis)
+{
+    if (!live_volume(dst) || !live_volume(src) || dst->fmt != src->fmt) return vktInvalidValue;
+    if ((int)axis < vktAxisX || (int)axis > vktAxisZ) return vktInvalidValue;
+    for (int a = 0; a < 3; ++a)
+        if (dst->dims[a] != src->dims[a]) return vktInvalidValue;
+    const int64_t bytes = cells(src) * vkt::cell_bytes(src->fmt);
+    const char* d0 = static_cast<const char*>(dst->dev);
+    const char* s0 = static_cast<const char*>(src->dev);
+    if (d0 != s0 && d0 < s0 + bytes && s0 < d0 + bytes) return vktInvalidValue;  // partial overlap
+    return from_hip(vkt::launch_flip(src->dev, dst->dev, src->fmt, src->dims, (int)axis,
+                                     state().stream));
+}
+
+vktError vktResampleSV(vktStructuredVolume dst, vktStructuredVolume src)
+{
+    return vktResample(dst, src);
+}
+
+vktError vktFlipSV(vktStructuredVolume dst, vktStructuredVolume src, vktAxis axis)
+{
+    return vktFlip(dst, src, axis);
+}
+
 vktError vktSetSeparable(int enable)
 {
     state().separable = enable != 0;

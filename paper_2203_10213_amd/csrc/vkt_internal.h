@@ -154,6 +154,12 @@ hipError_t launch_fill_range(void* dst, int cell_bytes, int32_t X, int32_t Y,
                              const int32_t first[3], const int32_t last[3],
                              uint32_t raw_bits, hipStream_t s);
 hipError_t launch_filter_valu(const FilterJob& j, hipStream_t s);
+// Resample src (dims in) to dst (dims out), same format; Flip along axis
+// (0 = x, 1 = y, 2 = z), in place when src == dst.
+hipError_t launch_resample(const void* src, void* dst, vktDataFormat f, const int32_t in[3],
+                           const int32_t out[3], hipStream_t s);
+hipError_t launch_flip(const void* src, void* dst, vktDataFormat f, const int32_t dims[3],
+                       int axis, hipStream_t s);
 // Rank-1 filters as three one-dimensional passes (opt-in, vktSetSeparable).
 hipError_t launch_filter_sep(const FilterJob& j, hipStream_t s);
 // 8-bit dot-product path for uint8 volumes with small integer filters.

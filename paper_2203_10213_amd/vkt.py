@@ -20,6 +20,7 @@ vktNoError, vktInvalidValue, vktOutOfMemory, vktDeviceError, vktUnsupported = ra
 vktDataFormatUInt8, vktDataFormatUInt16, vktDataFormatFloat32 = range(3)
 vktAddressModeClamp, vktAddressModeWrap, vktAddressModeMirror, vktAddressModeBorder = range(4)
 vktPrecisionAuto, vktPrecisionFP32, vktPrecisionSplitBF16, vktPrecisionSplitBF16x6 = range(4)
+vktAxisX, vktAxisY, vktAxisZ = range(3)
 
 MODES = {"clamp": vktAddressModeClamp, "wrap": vktAddressModeWrap,
          "mirror": vktAddressModeMirror, "border": vktAddressModeBorder}
@@ -49,6 +50,10 @@ SIGNATURES = {
     "vktApplyFilter": [_P, _P, _P, ctypes.c_int],
     "vktApplyFilterRange": [_P, _P, _P, _I32, _I32, _I32, _I32, _I32, _I32, ctypes.c_int],
     "vktApplyFilterBatched": [_I32, _PP, _PP, _PP, ctypes.c_int],
+    "vktResample": [_P, _P],
+    "vktFlip": [_P, _P, ctypes.c_int],
+    "vktResampleSV": [_P, _P],
+    "vktFlipSV": [_P, _P, ctypes.c_int],
     "vktSetAutotune": [ctypes.c_int],
     "vktSetSeparable": [ctypes.c_int],
     "vktGetSeparable": [ctypes.POINTER(ctypes.c_int)],
@@ -217,6 +222,19 @@ def vktApplyFilterBatched(dsts, srcs, filts, mode=vktAddressModeClamp):
         "vktApplyFilterBatched")
 
 
+def vktResample(dst, src):
+    _ok(lib().vktResample(dst, src), "vktResample")
+
+
+def vktFlip(dst, src, axis):
+    """axis: 0 / vktAxisX, 1 / vktAxisY, 2 / vktAxisZ; dst == src flips in place."""
+    _ok(lib().vktFlip(dst, src, int(axis)), "vktFlip")
+
+
+vktResampleSV = vktResample
+vktFlipSV = vktFlip
+
+
 # ------------------------------------------------------------- thread state --
 
 def vktSetStream(stream):
@@ -295,5 +313,30 @@ def apply_filter(dst, src, weights, mode="clamp", divisor=None, roi=None):
             vktApplyFilterRange(hd, hs, hf, roi[0], roi[1], mode)
     finally:
         vktFilterDestroy(hf)
+        vktStructuredVolumeDestroy(hd)
+        vktStructuredVolumeDestroy(hs)
+
+
+def resample(dst, src):
+    """Resample device tensor src onto dst's shape on torch's current stream."""
+    vktSetStream(torch.cuda.current_stream())
+    hs = volume_from_tensor(src)
+    hd = volume_from_tensor(dst)
+    try:
+        vktResample(hd, hs)
+    finally:
+        vktStructuredVolumeDestroy(hd)
+        vktStructuredVolumeDestroy(hs)
+
+
+def flip(dst, src, axis):
+    """Flip device tensor src into dst (dst may be src) along axis 0 = x,
+    1 = y, 2 = z on torch's current stream."""
+    vktSetStream(torch.cuda.current_stream())
+    hs = volume_from_tensor(src)
+    hd = volume_from_tensor(dst)
+    try:
+        vktFlip(hd, hs, axis)
+    finally:
         vktStructuredVolumeDestroy(hd)
         vktStructuredVolumeDestroy(hs)

@@ -52,6 +52,12 @@ def test_null_handles_rejected_without_gpu(vkt):
     bogus = 0x1000
     assert L.vktApplyFilter(bogus, bogus, bogus, 0) == vkt.vktInvalidValue
     assert L.vktApplyFilterRange(bogus, bogus, bogus, 0, 0, 0, 1, 1, 1, 0) == vkt.vktInvalidValue
+    for f in (L.vktResample, L.vktResampleSV):
+        assert f(None, None) == vkt.vktInvalidValue
+        assert f(bogus, bogus) == vkt.vktInvalidValue
+    for f in (L.vktFlip, L.vktFlipSV):
+        assert f(None, None, 0) == vkt.vktInvalidValue
+        assert f(bogus, bogus, 1) == vkt.vktInvalidValue
     # bad k / NULL weights fail before any device allocation
     assert L.vktFilterCreate(None, 3, None) == vkt.vktInvalidValue
     assert L.vktStructuredVolumeCreate(None, 4, 4, 4, 0, 1, 1, 1, 0, 1) == vkt.vktInvalidValue
