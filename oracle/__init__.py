@@ -17,7 +17,7 @@ from ._build import LIB, build_oracle
 
 __all__ = ["MODES", "correlate", "correlate_points", "store_float_filter",
            "store_int_filter", "apply_filter", "fill_raw", "fill_range",
-           "address", "lib"]
+           "address", "resample", "flip", "brick_grid", "brick_decompose", "lib"]
 
 MODES = {"clamp": 0, "wrap": 1, "mirror": 2, "border": 3}
 _FMT = {np.dtype(np.uint8): 0, np.dtype(np.uint16): 1,
@@ -51,9 +51,12 @@ def lib():
     L.vkto_resample_linear.argtypes = [vp, ctypes.c_int, i64, i64, i64, i64, i64, i64,
                                        dp, dp]
     L.vkto_flip.argtypes = [vp, ctypes.c_int, i64, i64, i64, ctypes.c_int, vp]
+    L.vkto_brick.argtypes = [vp, ctypes.c_int, i64, i64, i64, i64, i64, i64, i64, i64, i64,
+                             ctypes.c_int, vp]
     for f in ("vkto_correlate", "vkto_correlate_points",
               "vkto_store_float_filter", "vkto_store_int_filter",
-              "vkto_fill_raw", "vkto_fill_range", "vkto_resample_linear", "vkto_flip"):
+              "vkto_fill_raw", "vkto_fill_range", "vkto_resample_linear", "vkto_flip",
+              "vkto_brick"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -190,4 +193,36 @@ def flip(src, axis):
     out = np.empty_like(src)
     _check(lib().vkto_flip(src.ctypes.data, _FMT[src.dtype], X, Y, Z, int(axis),
                            out.ctypes.data), "vkto_flip")
+    return out
+
+
+def brick_grid(dims, brick):
+    """Bricks per axis: ceil(dim / brick) for dims, brick = (x, y, z)."""
+    return tuple(-(-int(d) // int(b)) for d, b in zip(dims, brick))
+
+
+def brick_decompose(src, brick, ghost=(0, 0, 0), mode="clamp"):
+    """Split src (Z, Y, X) into bricks of brick = (BX, BY, BZ) interior cells
+    (the last brick on an axis keeps the remainder), each with ghost =
+    (gx, gy, gz) extra cells on both sides read through the address mode
+    (paper Sec. 3.2 BrickDecompose).  Returns the bricks in order of brick
+    index bx + nbx * (by + nby * bz), each a (Z, Y, X) array."""
+    src = _volume(src)
+    Z, Y, X = src.shape
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    (BX, BY, BZ), (gx, gy, gz) = brick, ghost
+    nbx, nby, nbz = brick_grid((X, Y, Z), brick)
+    out = []
+    for bz in range(nbz):
+        for by in range(nby):
+            for bx in range(nbx):
+                ix = min(BX, X - bx * BX)
+                iy = min(BY, Y - by * BY)
+                iz = min(BZ, Z - bz * BZ)
+                b = np.empty((iz + 2 * gz, iy + 2 * gy, ix + 2 * gx), src.dtype)
+                _check(lib().vkto_brick(src.ctypes.data, _FMT[src.dtype], X, Y, Z,
+                                        bx * BX - gx, by * BY - gy, bz * BZ - gz,
+                                        ix + 2 * gx, iy + 2 * gy, iz + 2 * gz, m,
+                                        b.ctypes.data), "vkto_brick")
+                out.append(b)
     return out

@@ -343,3 +343,28 @@ int vkto_flip(const void* src, int fmt, int64_t X, int64_t Y, int64_t Z, int axi
             }
     return 0;
 }
+
+/* ---- BrickDecompose: one brick with ghost cells (Sec. 3.2) --------------- */
+
+int vkto_brick(const void* src, int fmt, int64_t X, int64_t Y, int64_t Z, int64_t x0,
+               int64_t y0, int64_t z0, int64_t nx, int64_t ny, int64_t nz, int mode,
+               void* dst)
+{
+    if (!src || !dst || !valid_fmt(fmt) || X < 1 || Y < 1 || Z < 1 || nx < 0 || ny < 0 ||
+        nz < 0 || mode < VKTO_CLAMP || mode > VKTO_BORDER)
+        return -1;
+    const size_t cb = fmt == VKTO_U8 ? 1 : fmt == VKTO_U16 ? 2 : fmt == VKTO_F32 ? 4 : 8;
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t j = 0; j < ny; ++j)
+            for (int64_t i = 0; i < nx; ++i) {
+                char* out = (char*)dst + (i + nx * (j + ny * k)) * cb;
+                const int64_t sx = vkto_address(x0 + i, X, mode);
+                const int64_t sy = vkto_address(y0 + j, Y, mode);
+                const int64_t sz = vkto_address(z0 + k, Z, mode);
+                if (sx < 0 || sy < 0 || sz < 0)
+                    memset(out, 0, cb);
+                else
+                    memcpy(out, (const char*)src + (sx + X * (sy + Y * sz)) * cb, cb);
+            }
+    return 0;
+}

@@ -19,6 +19,8 @@
  *     cell coordinates, to one value mapped through the volume's value range.
  *   Resample, Flip -- paper Sec. 3.2 (core and transform algorithms) and the
  *     structured-volume benchmarks of Sec. 4.
+ *   BrickDecompose -- paper Sec. 3.2 (domain decomposition algorithms): a
+ *     volume split into bricks, optionally with ghost cells around each.
  *
  * Layout: a volume of dims X*Y*Z is a dense array, x fastest:
  *   index(x, y, z) = x + X*(y + Y*z).
@@ -96,6 +98,16 @@ int vkto_resample_linear(const void* src, int fmt, int64_t X, int64_t Y, int64_t
  * typed by fmt and must not overlap. */
 int vkto_flip(const void* src, int fmt, int64_t X, int64_t Y, int64_t Z, int axis,
               void* dst);
+
+/* One brick of a brick decomposition with ghost cells (paper Sec. 3.2,
+ * domain decomposition algorithms): dst is the box of nx*ny*nz cells whose
+ * first cell sits at source coordinate (x0, y0, z0) -- which may be negative
+ * or reach past the volume, so that the box holds ghost cells around a brick
+ * interior -- each cell read through the address map (BORDER outside: 0).
+ * dst is typed by fmt, x fastest, and must not overlap src. */
+int vkto_brick(const void* src, int fmt, int64_t X, int64_t Y, int64_t Z, int64_t x0,
+               int64_t y0, int64_t z0, int64_t nx, int64_t ny, int64_t nz, int mode,
+               void* dst);
 
 #ifdef __cplusplus
 }
