@@ -350,8 +350,9 @@ def run_transforms(args, vkt, torch):
     """Resample by one half on every axis and Flip along the longest axis
     (x for these cubes: the first of the equal extents) of the 512^3 uint8
     phantom and the 512^3 float32 noise field; one step = the four calls.
-    Value: source voxels per second over the step.  Flips along y and z are
-    timed apart (per_case)."""
+    Value: source voxels per second over the step.  Flips along y and z and
+    BrickDecompose into 64^3 bricks with 2-cell ghosts are timed apart
+    (per_case)."""
     import numpy as np
     from paper_2203_10213_amd import synth
     S = synth.SEEDS
@@ -373,6 +374,23 @@ def run_transforms(args, vkt, torch):
             ops.append(dict(case=f"flip_{'xyz'[ax]}_{name}",
                             fn=lambda hf=hf, hs=hs, ax=ax: vkt.vktFlip(hf, hs, ax),
                             voxels=n, bytes=2 * n * cb, step=ax == longest))
+        # BrickDecompose into 64^3 bricks with 2-cell ghosts (the 5^3 filter's
+        # radius): outside the step; bytes = one cell read per brick cell
+        # written, ghosts included
+        B, G = (64, 64, 64), (2, 2, 2)
+        nb = vkt.vktBrickDecomposeGetNumBricks(hs, B)
+        bricks = []
+        for bz in range(nb[2]):
+            for by in range(nb[1]):
+                for bx in range(nb[0]):
+                    dx, dy, dz = vkt.vktBrickDecomposeGetBrickDims(hs, B, G, (bx, by, bz))
+                    bricks.append(torch.empty((dz, dy, dx), dtype=src.dtype, device=src.device))
+        hb = [vkt.volume_from_tensor(t) for t in bricks]
+        handles += hb
+        nbc = sum(t.numel() for t in bricks)
+        ops.append(dict(case=f"brick_decompose_64_g2_{name}",
+                        fn=lambda hb=hb, hs=hs: vkt.vktBrickDecompose(hb, hs, B, G, "clamp"),
+                        voxels=n, bytes=2 * nbc * cb, step=False))
     torch.cuda.synchronize()
 
     def timed(op_list, K, W):

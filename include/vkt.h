@@ -233,6 +233,48 @@ vktError vktFlip(vktStructuredVolume dst, vktStructuredVolume src, vktAxis axis)
 vktError vktResampleSV(vktStructuredVolume dst, vktStructuredVolume src);
 vktError vktFlipSV(vktStructuredVolume dst, vktStructuredVolume src, vktAxis axis);
 
+/* ---- BrickDecompose (paper Sec. 3.2 domain decomposition algorithms) ---- */
+
+/* Bricks of (brickX, brickY, brickZ) interior cells tile the volume: brick
+ * (bx, by, bz) starts at cell (bx*brickX, by*brickY, bz*brickZ), and the last
+ * brick on an axis keeps the remainder, so there are ceil(dim / brick)
+ * bricks per axis.  A brick volume holds its interior plus ghost cells on
+ * both sides of each axis (ghostX/Y/Z per side), taken from the source
+ * through the address mode (border: 0).  With ghosts of at least the filter
+ * radius, ApplyFilter on a brick reproduces the whole-volume ApplyFilter on
+ * the brick's interior, whatever mode the brick is filtered with.
+ * Errors (all three calls): vktInvalidValue for a bad handle or NULL pointer,
+ * a brick size < 1 or a ghost width < 0. */
+vktError vktBrickDecomposeGetNumBricks(vktStructuredVolume src, int32_t brickX,
+                                       int32_t brickY, int32_t brickZ,
+                                       int32_t* numX, int32_t* numY,
+                                       int32_t* numZ);
+/* Dims of brick (bx, by, bz), ghosts included:
+ * min(brick, dim - b*brick) + 2*ghost per axis.  vktInvalidValue also for a
+ * brick index outside the grid. */
+vktError vktBrickDecomposeGetBrickDims(vktStructuredVolume src, int32_t brickX,
+                                       int32_t brickY, int32_t brickZ,
+                                       int32_t ghostX, int32_t ghostY,
+                                       int32_t ghostZ, int32_t bx, int32_t by,
+                                       int32_t bz, int32_t* dimX, int32_t* dimY,
+                                       int32_t* dimZ);
+/* Write every brick: bricks[bx + numX*(by + numY*bz)] for all n =
+ * numX*numY*numZ bricks, each a volume of src's format with exactly the
+ * dims above (created by the caller, e.g. with vktStructuredVolumeCreate).
+ * One launch per 128 bricks, no device allocation.  Errors: as above, and
+ * vktInvalidValue when n differs from the brick count, a brick has the wrong
+ * dims or format, a mode is out of range, or brick buffers overlap each
+ * other or src. */
+vktError vktBrickDecompose(int32_t n, const vktStructuredVolume* bricks,
+                           vktStructuredVolume src, int32_t brickX,
+                           int32_t brickY, int32_t brickZ, int32_t ghostX,
+                           int32_t ghostY, int32_t ghostZ, vktAddressMode mode);
+/* The paper's C99 name; identical to vktBrickDecompose. */
+vktError vktBrickDecomposeSV(int32_t n, const vktStructuredVolume* bricks,
+                             vktStructuredVolume src, int32_t brickX,
+                             int32_t brickY, int32_t brickZ, int32_t ghostX,
+                             int32_t ghostY, int32_t ghostZ, vktAddressMode mode);
+
 /* ---- per-thread execution state (paper Sec. 3.1 ExecutionPolicy) -------- */
 
 /* stream is a hipStream_t (NULL = the default stream). */

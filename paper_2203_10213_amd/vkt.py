@@ -50,6 +50,11 @@ SIGNATURES = {
     "vktApplyFilter": [_P, _P, _P, ctypes.c_int],
     "vktApplyFilterRange": [_P, _P, _P, _I32, _I32, _I32, _I32, _I32, _I32, ctypes.c_int],
     "vktApplyFilterBatched": [_I32, _PP, _PP, _PP, ctypes.c_int],
+    "vktBrickDecomposeGetNumBricks": [_P, _I32, _I32, _I32, _PI, _PI, _PI],
+    "vktBrickDecomposeGetBrickDims": [_P, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _I32,
+                                      _PI, _PI, _PI],
+    "vktBrickDecompose": [_I32, _PP, _P, _I32, _I32, _I32, _I32, _I32, _I32, ctypes.c_int],
+    "vktBrickDecomposeSV": [_I32, _PP, _P, _I32, _I32, _I32, _I32, _I32, _I32, ctypes.c_int],
     "vktResample": [_P, _P],
     "vktFlip": [_P, _P, ctypes.c_int],
     "vktResampleSV": [_P, _P],
@@ -231,6 +236,35 @@ def vktFlip(dst, src, axis):
     _ok(lib().vktFlip(dst, src, int(axis)), "vktFlip")
 
 
+def vktBrickDecomposeGetNumBricks(src, brick):
+    """brick = (x, y, z) interior cells; returns bricks per axis (x, y, z)."""
+    n = [ctypes.c_int32() for _ in range(3)]
+    _ok(lib().vktBrickDecomposeGetNumBricks(src, *[int(b) for b in brick],
+                                            *[ctypes.byref(v) for v in n]),
+        "vktBrickDecomposeGetNumBricks")
+    return tuple(v.value for v in n)
+
+
+def vktBrickDecomposeGetBrickDims(src, brick, ghost, index):
+    """Dims (x, y, z) of brick index = (bx, by, bz), ghosts included."""
+    d = [ctypes.c_int32() for _ in range(3)]
+    _ok(lib().vktBrickDecomposeGetBrickDims(src, *[int(b) for b in brick],
+                                            *[int(g) for g in ghost], *[int(i) for i in index],
+                                            *[ctypes.byref(v) for v in d]),
+        "vktBrickDecomposeGetBrickDims")
+    return tuple(v.value for v in d)
+
+
+def vktBrickDecompose(bricks, src, brick, ghost=(0, 0, 0), mode=vktAddressModeClamp):
+    """bricks: handles in order bx + numX * (by + numY * bz)."""
+    n = len(bricks)
+    arr = ctypes.c_void_p * max(n, 1)
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    _ok(lib().vktBrickDecompose(n, arr(*bricks), src, *[int(b) for b in brick],
+                                *[int(g) for g in ghost], m), "vktBrickDecompose")
+
+
+vktBrickDecomposeSV = vktBrickDecompose
 vktResampleSV = vktResample
 vktFlipSV = vktFlip
 
@@ -340,3 +374,26 @@ def flip(dst, src, axis):
     finally:
         vktStructuredVolumeDestroy(hd)
         vktStructuredVolumeDestroy(hs)
+
+
+def brick_decompose(src, brick, ghost=(0, 0, 0), mode="clamp"):
+    """Bricks of device tensor src (Z, Y, X) as new device tensors, in order
+    bx + numX * (by + numY * bz), on torch's current stream."""
+    vktSetStream(torch.cuda.current_stream())
+    hs = volume_from_tensor(src)
+    out, hb = [], []
+    try:
+        nx, ny, nz = vktBrickDecomposeGetNumBricks(hs, brick)
+        for bz in range(nz):
+            for by in range(ny):
+                for bx in range(nx):
+                    dx, dy, dz = vktBrickDecomposeGetBrickDims(hs, brick, ghost, (bx, by, bz))
+                    t = torch.empty((dz, dy, dx), dtype=src.dtype, device=src.device)
+                    out.append(t)
+                    hb.append(volume_from_tensor(t))
+        vktBrickDecompose(hb, hs, brick, ghost, mode)
+    finally:
+        for h in hb:
+            vktStructuredVolumeDestroy(h)
+        vktStructuredVolumeDestroy(hs)
+    return out

@@ -58,6 +58,12 @@ def test_null_handles_rejected_without_gpu(vkt):
     for f in (L.vktFlip, L.vktFlipSV):
         assert f(None, None, 0) == vkt.vktInvalidValue
         assert f(bogus, bogus, 1) == vkt.vktInvalidValue
+    assert L.vktBrickDecompose(0, None, None, 1, 1, 1, 0, 0, 0, 0) == vkt.vktInvalidValue
+    assert L.vktBrickDecomposeSV(1, None, bogus, 1, 1, 1, 0, 0, 0, 0) == vkt.vktInvalidValue
+    assert L.vktBrickDecomposeGetNumBricks(bogus, 1, 1, 1, None, None, None) \
+        == vkt.vktInvalidValue
+    assert L.vktBrickDecomposeGetBrickDims(None, 1, 1, 1, 0, 0, 0, 0, 0, 0, None, None, None) \
+        == vkt.vktInvalidValue
     # bad k / NULL weights fail before any device allocation
     assert L.vktFilterCreate(None, 3, None) == vkt.vktInvalidValue
     assert L.vktStructuredVolumeCreate(None, 4, 4, 4, 0, 1, 1, 1, 0, 1) == vkt.vktInvalidValue
