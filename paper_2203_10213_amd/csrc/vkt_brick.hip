@@ -11,9 +11,10 @@
 // batched form directly.
 //
 // One launch covers up to kMaxBricks bricks, whose destination pointers
-// travel in the kernel arguments (no device allocation).  Block z picks the
-// brick, block x a run of 64 of its rows; the block's 64 x 4 threads copy 4
-// rows at a time, lanes along x.  Interior source reads are contiguous
+// travel in the kernel arguments (no device allocation).  A workgroup copies
+// a run of 64 rows of one brick, its 64 x 4 threads 4 rows at a time, lanes
+// along x; workgroups are numbered so that the same run of all bricks of a
+// launch lands on one XCD.  Interior source reads are contiguous
 // along x, brick writes contiguous; the address mode is applied per
 // coordinate.
 #include "vkt_internal.h"
@@ -35,6 +36,7 @@ struct BrickArgs {
     int32_t G[3];         // ghost cells per side
     int32_t nbx, nby;     // bricks along x, y
     int32_t first;        // brick index of dst[0]
+    int32_t count;        // bricks of this launch
     int32_t mode;
     void* dst[kMaxBricks];
 };
@@ -57,6 +59,15 @@ __device__ inline int brick_addr(int64_t i, int64_t n, int mode)
     return -1;
 }
 
+// Workgroup id -> logical id such that consecutive logical ids run on one
+// XCD (the dispatcher deals workgroups to the 8 XCDs round-robin, each XCD
+// with its own L2).
+__device__ inline uint32_t xcd_group(uint32_t b, uint32_t n)
+{
+    const uint32_t q = n / 8, rem = n % 8, xcd = b % 8, idx = b / 8;
+    return xcd < rem ? xcd * (q + 1) + idx : rem * (q + 1) + (xcd - rem) * q + idx;
+}
+
 // Rows of a brick per workgroup: 64, i.e. 16 per thread row lane.
 constexpr int kRowsPerWG = 64;
 constexpr int kRowsPerThread = kRowsPerWG / 4;
@@ -64,17 +75,22 @@ constexpr int kRowsPerThread = kRowsPerWG / 4;
 template <typename T>
 __global__ __launch_bounds__(kNT) void brick_kernel(BrickArgs a)
 {
-    const int b = a.first + (int)blockIdx.z;
+    // logical id = brick + count * chunk: the bricks of one chunk (row run),
+    // which share the source cache lines at their x faces, sit on one XCD
+    const uint32_t logical = xcd_group(blockIdx.x, gridDim.x);
+    const int bl = (int)(logical % (uint32_t)a.count);
+    const int chunk = (int)(logical / (uint32_t)a.count);
+    const int b = a.first + bl;
     const int bx = b % a.nbx, by = (b / a.nbx) % a.nby, bz = b / (a.nbx * a.nby);
     const int o[3] = {bx * a.B[0] - a.G[0], by * a.B[1] - a.G[1], bz * a.B[2] - a.G[2]};
     const int dx = min(a.B[0], a.X - bx * a.B[0]) + 2 * a.G[0];
     const int dy = min(a.B[1], a.Y - by * a.B[1]) + 2 * a.G[1];
     const int dz = min(a.B[2], a.Z - bz * a.B[2]) + 2 * a.G[2];
     const int64_t nrows = (int64_t)dy * dz;
-    const int64_t r0 = (int64_t)blockIdx.x * kRowsPerWG + threadIdx.y;
+    const int64_t r0 = (int64_t)chunk * kRowsPerWG + threadIdx.y;
     if (r0 >= nrows) return;
     const T* __restrict__ src = static_cast<const T*>(a.src);
-    T* __restrict__ dst = static_cast<T*>(a.dst[blockIdx.z]);
+    T* __restrict__ dst = static_cast<T*>(a.dst[bl]);
     // this thread's rows r0 + 4 i: source row offsets (-1: outside, zeros)
     int64_t soff[kRowsPerThread];
 #pragma unroll
@@ -129,15 +145,16 @@ hipError_t launch_bricks(BrickArgs& a, const std::vector<void*>& dsts, hipStream
 {
     const int64_t rows_max =
         (int64_t)(std::min(a.B[1], a.Y) + 2 * a.G[1]) * (std::min(a.B[2], a.Z) + 2 * a.G[2]);
-    const int64_t gx = (rows_max + kRowsPerWG - 1) / kRowsPerWG;
-    if (gx > INT32_MAX) return hipErrorInvalidValue;
+    const int64_t chunks = (rows_max + kRowsPerWG - 1) / kRowsPerWG;
+    if (chunks * kMaxBricks > INT32_MAX) return hipErrorInvalidValue;
     const int n = (int)dsts.size();
     for (int f = 0; f < n; f += kMaxBricks) {
         const int cnt = std::min(kMaxBricks, n - f);
         a.first = f;
+        a.count = cnt;
         for (int i = 0; i < cnt; ++i) a.dst[i] = dsts[f + i];
-        hipLaunchKernelGGL((brick_kernel<T>), dim3((unsigned)gx, 1, (unsigned)cnt), dim3(64, 4),
-                           0, s, a);
+        hipLaunchKernelGGL((brick_kernel<T>), dim3((unsigned)(chunks * cnt)), dim3(64, 4), 0, s,
+                           a);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
