@@ -25,6 +25,7 @@
 #include "vkt_internal.h"
 
 #include <type_traits>
+#include <utility>
 
 namespace vkt {
 namespace {
@@ -90,10 +91,29 @@ __device__ inline float buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off)
 __device__ inline void load_factor(const float* p, float (&f)[16])
 {
     typedef uint32_t v16 __attribute__((ext_vector_type(16)));
+    // the address is uniform; readfirstlane keeps it in SGPRs even where
+    // register pressure would otherwise leave a copy in VGPRs
+    // (readfirstlane returns int: widen through uint32_t, not by sign)
+    const uint64_t a = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32));
+    const uint64_t sa = (uint64_t)lo | ((uint64_t)hi << 32);
     v16 r;
-    asm volatile("s_load_dwordx16 %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=&s"(r) : "s"(p));
+    asm volatile("s_load_dwordx16 %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=&s"(r) : "s"(sa));
 #pragma unroll
     for (int q = 0; q < 16; ++q) f[q] = __uint_as_float(r[q]);
+}
+
+template <typename F, int... I>
+__device__ __attribute__((always_inline)) inline void static_for_impl(
+    F& f, std::integer_sequence<int, I...>)
+{
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __attribute__((always_inline)) inline void static_for(F&& f)
+{
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
 __device__ inline uint32_t udiv(uint32_t n, UDiv d)
@@ -104,7 +124,7 @@ __device__ inline uint32_t udiv(uint32_t n, UDiv d)
 
 // Stored value of one finished output (T exact integer for integer filters).
 template <typename T>
-__device__ inline T finish(float acc, const VolDesc& a)
+__device__ __attribute__((always_inline)) inline T finish(float acc, const VolDesc& a)
 {
     if constexpr (std::is_same<T, float>::value) {
         return a.epi == kEpiFloatDiv ? acc * a.inv_D : acc;
@@ -123,7 +143,7 @@ __device__ inline T finish(float acc, const VolDesc& a)
 
 // One tile-slab; f holds the factors u | v | t at offsets 0, 16, 32.
 template <typename T, int K>
-__device__ void sep_tile(const VolDesc& a, const float* __restrict__ f, int tile, int slab,
+__device__ __attribute__((always_inline)) inline void sep_tile(const VolDesc& a, const float* __restrict__ f, int tile, int slab,
                          float* lds)
 {
     using G = GeoS<K>;
@@ -153,7 +173,7 @@ __device__ void sep_tile(const VolDesc& a, const float* __restrict__ f, int tile
     }
     const int32_t plane_bytes = (int32_t)(plane * (int64_t)sizeof(T));  // < 2^31 (host check)
     float stage[G::NE];
-    auto gather = [&](int zi) {
+    auto gather = [&](int zi) __attribute__((always_inline)) {
         const int gz = addr_map(zi, a.Z, a.mode);  // -1 only for border: a zero plane
         const char* base = reinterpret_cast<const char*>(src) +
                            (gz < 0 ? 0 : (int64_t)gz * plane_bytes);
@@ -162,18 +182,26 @@ __device__ void sep_tile(const VolDesc& a, const float* __restrict__ f, int tile
 #pragma unroll
         for (int i = 0; i < G::NE; ++i) stage[i] = buf_load<T>(rs, goff[i]);
     };
-    auto put = [&](float* buf) {
+    auto put = [&](float* buf) __attribute__((always_inline)) {
 #pragma unroll
         for (int i = 0; i < G::NE; ++i) buf[loff[i]] = stage[i];
     };
 
+    // z ring in fixed registers: the z loop is unrolled by K, and at plane
+    // p = zi - zi_beg the ring entry of age c (output plane zi - c + r) sits
+    // in slot (c - p) mod K, so no entry moves between planes
     float acc[K][kVY][kVX];
-#pragma unroll
-    for (int c = 0; c < K; ++c)
-#pragma unroll
-        for (int vy = 0; vy < kVY; ++vy)
-#pragma unroll
-            for (int vx = 0; vx < kVX; ++vx) acc[c][vy][vx] = 0.f;
+
+    // k <= 7: the three factor vectors stay in SGPRs for the whole
+    // tile-slab; larger k loads each one before its pass (48 live weights
+    // would spill SGPRs)
+    constexpr bool kHoist = K <= 7;
+    float u[16], v[16], tw[16];
+    if constexpr (kHoist) {
+        load_factor(f, u);
+        load_factor(f + 16, v);
+        load_factor(f + 32, tw);
+    }
 
     const int zi_beg = zb - R, zi_end = ze + R;
     gather(zi_beg);
@@ -183,38 +211,37 @@ __device__ void sep_tile(const VolDesc& a, const float* __restrict__ f, int tile
 
     const int ox = x0 + kVX * tx, oy = y0 + kVY * ty;
     const bool vec = a.vec_ok && ox + kVX <= a.rx1;
-    for (int zi = zi_beg; zi < zi_end; ++zi) {
+
+    auto step = [&](int zi, auto U) __attribute__((always_inline)) {
+        constexpr int P = decltype(U)::value;  // plane index mod K
         const int cur = (zi - zi_beg) & 1;
         const float* A = lds + cur * G::A_CELLS;
 
         // ---- x pass over all staged rows: bx[row][x] = sum_a u[a] A[row][x + a]
-        {
-            float u[16];
-            load_factor(f, u);
+        if constexpr (!kHoist) load_factor(f, u);
 #pragma unroll
-            for (int i = 0; i < G::NXR; ++i) {
-                const int row = ty + kBY * i;
-                if (row < G::HY) {
-                    float wdw[4 * G::XR];
+        for (int i = 0; i < G::NXR; ++i) {
+            const int row = ty + kBY * i;
+            if (row < G::HY) {
+                float wdw[4 * G::XR];
 #pragma unroll
-                    for (int q = 0; q < G::XR; ++q) {
-                        const float4 v4 =
-                            *reinterpret_cast<const float4*>(A + row * G::P + kVX * tx + 4 * q);
-                        wdw[4 * q + 0] = v4.x;
-                        wdw[4 * q + 1] = v4.y;
-                        wdw[4 * q + 2] = v4.z;
-                        wdw[4 * q + 3] = v4.w;
-                    }
-                    float h[kVX];
-#pragma unroll
-                    for (int vx = 0; vx < kVX; ++vx) {
-                        h[vx] = 0.f;
-#pragma unroll
-                        for (int aa = 0; aa < K; ++aa) h[vx] = fmaf(u[aa], wdw[vx + aa], h[vx]);
-                    }
-                    *reinterpret_cast<float4*>(bx + row * kTX + kVX * tx) =
-                        make_float4(h[0], h[1], h[2], h[3]);
+                for (int q = 0; q < G::XR; ++q) {
+                    const float4 v4 =
+                        *reinterpret_cast<const float4*>(A + row * G::P + kVX * tx + 4 * q);
+                    wdw[4 * q + 0] = v4.x;
+                    wdw[4 * q + 1] = v4.y;
+                    wdw[4 * q + 2] = v4.z;
+                    wdw[4 * q + 3] = v4.w;
                 }
+                float h[kVX];
+#pragma unroll
+                for (int vx = 0; vx < kVX; ++vx) {
+                    h[vx] = u[0] * wdw[vx];
+#pragma unroll
+                    for (int aa = 1; aa < K; ++aa) h[vx] = fmaf(u[aa], wdw[vx + aa], h[vx]);
+                }
+                *reinterpret_cast<float4*>(bx + row * kTX + kVX * tx) =
+                    make_float4(h[0], h[1], h[2], h[3]);
             }
         }
         // next plane into the other staging buffer (read two barriers later)
@@ -222,49 +249,43 @@ __device__ void sep_tile(const VolDesc& a, const float* __restrict__ f, int tile
         if (zi + 2 < zi_end) gather(zi + 2);
         __syncthreads();
 
-        // ---- y pass: p[vy][vx] = sum_b v[b] bx[2 ty + vy + b][4 tx + vx]
-        float p[kVY][kVX];
-        {
-            float v[16];
-            load_factor(f + 16, v);
-            // stream the k + 1 rows: row j feeds output row 0 through v[j]
-            // and output row 1 through v[j - 1]
+        // ---- y pass: p[vy][vx] = sum_b v[b] bx[2 ty + vy + b][4 tx + vx],
+        // streaming the k + 1 rows (row j feeds output row vy through v[j - vy])
+        float pv[kVY][kVX];
+        if constexpr (!kHoist) load_factor(f + 16, v);
+#pragma unroll
+        for (int j = 0; j < kVY + K - 1; ++j) {
+            const float4 v4 = *reinterpret_cast<const float4*>(bx + (kVY * ty + j) * kTX + kVX * tx);
+            const float row[kVX] = {v4.x, v4.y, v4.z, v4.w};
+#pragma unroll
+            for (int vy = 0; vy < kVY; ++vy) {
+                const int b = j - vy;
+                if (b < 0 || b >= K) continue;
+#pragma unroll
+                for (int vx = 0; vx < kVX; ++vx)
+                    pv[vy][vx] = b == 0 ? v[0] * row[vx] : fmaf(v[b], row[vx], pv[vy][vx]);
+            }
+        }
+        // ---- z pass: age c feeds output plane zi - c + r; age 0 starts its
+        // sum (a slot it reuses was stored or is never stored)
+        const int c_lo = max(0, zi + R - ze + 1), c_hi = min(K - 1, zi + R - zb);
+        if constexpr (!kHoist) load_factor(f + 32, tw);
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            if (c < c_lo || c > c_hi) continue;
+            const int slot = ((c - P) % K + K) % K;
 #pragma unroll
             for (int vy = 0; vy < kVY; ++vy)
 #pragma unroll
-                for (int vx = 0; vx < kVX; ++vx) p[vy][vx] = 0.f;
-#pragma unroll
-            for (int j = 0; j < kVY + K - 1; ++j) {
-                const float4 v4 = *reinterpret_cast<const float4*>(bx + (kVY * ty + j) * kTX + kVX * tx);
-                const float row[kVX] = {v4.x, v4.y, v4.z, v4.w};
-#pragma unroll
-                for (int vy = 0; vy < kVY; ++vy) {
-                    const int b = j - vy;
-                    if (b < 0 || b >= K) continue;
-#pragma unroll
-                    for (int vx = 0; vx < kVX; ++vx) p[vy][vx] = fmaf(v[b], row[vx], p[vy][vx]);
-                }
-            }
-        }
-        // ---- z pass: ring slot c feeds output plane zi - c + r
-        {
-            float tw[16];
-            load_factor(f + 32, tw);
-            const int c_lo = max(0, zi + R - ze + 1), c_hi = min(K - 1, zi + R - zb);
-#pragma unroll
-            for (int c = 0; c < K; ++c) {
-                if (c < c_lo || c > c_hi) continue;
-#pragma unroll
-                for (int vy = 0; vy < kVY; ++vy)
-#pragma unroll
-                    for (int vx = 0; vx < kVX; ++vx)
-                        acc[c][vy][vx] = fmaf(tw[c], p[vy][vx], acc[c][vy][vx]);
-            }
+                for (int vx = 0; vx < kVX; ++vx)
+                    acc[slot][vy][vx] = c == 0 ? tw[0] * pv[vy][vx]
+                                               : fmaf(tw[c], pv[vy][vx], acc[slot][vy][vx]);
         }
 
-        // ---- the ring's oldest entry is output plane zo = zi - r
+        // ---- the oldest entry (age K - 1) is output plane zo = zi - r
         const int zo = zi - R;
         if (zo >= zb) {
+            constexpr int old = ((K - 1 - P) % K + K) % K;
             T* orow = dst + (int64_t)zo * plane;
 #pragma unroll
             for (int vy = 0; vy < kVY; ++vy) {
@@ -273,7 +294,7 @@ __device__ void sep_tile(const VolDesc& a, const float* __restrict__ f, int tile
                 T* o = orow + (int64_t)y * a.X + ox;
                 T r4[kVX];
 #pragma unroll
-                for (int vx = 0; vx < kVX; ++vx) r4[vx] = finish<T>(acc[K - 1][vy][vx], a);
+                for (int vx = 0; vx < kVX; ++vx) r4[vx] = finish<T>(acc[old][vy][vx], a);
                 if (vec) {
                     if constexpr (sizeof(T) == 1) {
                         *reinterpret_cast<uchar4*>(o) = make_uchar4(r4[0], r4[1], r4[2], r4[3]);
@@ -289,18 +310,14 @@ __device__ void sep_tile(const VolDesc& a, const float* __restrict__ f, int tile
                 }
             }
         }
-#pragma unroll
-        for (int c = K - 1; c > 0; --c)
-#pragma unroll
-            for (int vy = 0; vy < kVY; ++vy)
-#pragma unroll
-                for (int vx = 0; vx < kVX; ++vx) acc[c][vy][vx] = acc[c - 1][vy][vx];
-#pragma unroll
-        for (int vy = 0; vy < kVY; ++vy)
-#pragma unroll
-            for (int vx = 0; vx < kVX; ++vx) acc[0][vy][vx] = 0.f;
         // the x pass of the next plane overwrites bx; its staging buffer is full
         __syncthreads();
+    };
+
+    for (int zi = zi_beg; zi < zi_end; zi += K) {
+        static_for<K>([&](auto U) {
+            if (zi + decltype(U)::value < zi_end) step(zi + decltype(U)::value, U);
+        });
     }
 }
 
