@@ -213,15 +213,25 @@ def test_c2a_ct_phantom_box27_full(orc):
 
 
 def test_c2b_smoothed_noise_gauss5_sampled(orc):
-    """512^3 float32 smoothed noise, 5^3 Gaussian sigma 1.5: 200k sampled
-    cells plus all corners/edges against the oracle."""
+    """512^3 float32 smoothed noise, 5^3 Gaussian sigma 1.5, plain FP32,
+    split and rank-1 forms: 200k sampled cells plus all corners/edges against
+    the oracle."""
     import torch
     from paper_2203_10213_amd import synth
     src_t = synth.smoothed_noise_f32(512, 4.0, synth.SEEDS["c2b"], device="cuda")
     src = src_t.cpu().numpy()
     w = synth.gaussian_weights(5, 1.5)
-    out = run_filter(src, w, "clamp", src_t=src_t)
     pts = sample_points(src.shape, 200000, 77)
-    check_against_oracle(orc, src, w, "clamp", out, pts=pts, what="C2b")
+    for prec in ("fp32", "auto"):   # the plain VALU form (as benchmarked) and the split form
+        out = run_filter(src, w, "clamp", precision=prec, src_t=src_t)
+        check_against_oracle(orc, src, w, "clamp", out, pts=pts, what=f"C2b {prec}")
+    # the rank-1 form of the same Gaussian
+    from paper_2203_10213_amd import vkt
+    vkt.vktSetSeparable(True)
+    try:
+        out = run_filter(src, w, "clamp", src_t=src_t)
+    finally:
+        vkt.vktSetSeparable(False)
+    check_against_oracle(orc, src, w, "clamp", out, pts=pts, what="C2b rank-1")
     del src_t
     torch.cuda.empty_cache()

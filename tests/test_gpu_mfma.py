@@ -101,27 +101,31 @@ def test_fp32_precision_forces_vector_path(orc):
     assert not np.array_equal(a, b)
 
 
-def test_c3a_blob_field_dense7_sampled(orc):
-    """1024^3 float32 blob field, dense 7^3 unit-L1 weights, both split
-    variants against the oracle on sampled cells (plus corners/edges)."""
+def test_c3_blob_field_dense7_dense9_sampled(orc):
+    """1024^3 float32 blob field, dense 7^3 and 9^3 unit-L1 weights, both
+    split variants and the FP32 form against the oracle on sampled cells
+    (plus corners/edges)."""
     import torch
     from paper_2203_10213_amd import synth
     src_t = synth.blob_field_f32(1024, 64, synth.SEEDS["c3"], device="cuda")
     src = src_t.cpu().numpy()
-    w = synth.random_l1(7, synth.SEEDS["c3a_w"])
     pts = sample_points(src.shape, 20000, 31)
-    for prec, tol in (("splitbf16", 1e-5), ("splitbf16x6", 1e-6), ("fp32", 1e-5)):
-        out = run_filter(src, w, "clamp", precision=prec, src_t=src_t)
-        e = check_against_oracle(orc, src, w, "clamp", out, pts=pts, tol=tol, what=prec)
-        print(f"C3a {prec}: max error / sum|w||s| = {e:.3g}")
+    for k, seed in ((7, synth.SEEDS["c3a_w"]), (9, synth.SEEDS["c3b_w"])):
+        w = synth.random_l1(k, seed)
+        for prec, tol in (("splitbf16", 1e-5), ("splitbf16x6", 1e-6), ("fp32", 1e-5)):
+            out = run_filter(src, w, "clamp", precision=prec, src_t=src_t)
+            e = check_against_oracle(orc, src, w, "clamp", out, pts=pts, tol=tol,
+                                     what=f"k={k} {prec}")
+            print(f"C3 k={k} {prec}: max error / sum|w||s| = {e:.3g}")
+            del out
     del src_t
     torch.cuda.empty_cache()
 
 
 def test_c5_ellipsoid_u16_gauss11_subblocks(orc):
     """2048 x 2048 x 1024 uint16 ellipsoid phantom, 11^3 Gaussian sigma 2.5
-    on the split path: 64 32^3 sub-blocks (the 8 corner blocks and 56 random
-    ones) checked cell by cell, within 1 LSB."""
+    on the split path and on the rank-1 form: 64 32^3 sub-blocks (the 8
+    corner blocks and 56 random ones) checked cell by cell, within 1 LSB."""
     import torch
     from paper_2203_10213_amd import synth, vkt
     src_t = synth.ellipsoid_phantom_u16((1024, 2048, 2048), 5000, synth.SEEDS["c5"],
@@ -131,6 +135,13 @@ def test_c5_ellipsoid_u16_gauss11_subblocks(orc):
     dst_t = torch.empty_like(src_t)
     vkt.vktSetPrecision("splitbf16")
     vkt.apply_filter(dst_t, src_t, w, "clamp")
+    # the rank-1 form of the same (separable) filter, on the same blocks
+    sep_t = torch.empty_like(src_t)
+    vkt.vktSetSeparable(True)
+    try:
+        vkt.apply_filter(sep_t, src_t, w, "clamp")
+    finally:
+        vkt.vktSetSeparable(False)
     torch.cuda.synchronize()
     Z, Y, X = src_t.shape
     g = np.random.default_rng(synth.SEEDS["c5_blocks"])
@@ -147,8 +158,9 @@ def test_c5_ellipsoid_u16_gauss11_subblocks(orc):
         sub = src_t.view(torch.int16)[idx[0]][:, idx[1]][:, :, idx[2]].cpu().numpy().view(np.uint16)
         T, _ = orc.correlate(sub, w.astype(np.float64), "clamp")  # halo makes clamp exact
         want = orc.store_float_filter(T[r:-r, r:-r, r:-r], np.uint16)
-        got = dst_t.view(torch.int16)[bz:bz + 32, by:by + 32, bx:bx + 32].cpu().numpy().view(np.uint16)
-        diff = np.abs(got.astype(np.int64) - want.astype(np.int64))
-        assert diff.max() <= 1, (bx, by, bz, diff.max())
-    del src_t, dst_t
+        for name, out_t in (("split", dst_t), ("rank-1", sep_t)):
+            got = out_t.view(torch.int16)[bz:bz + 32, by:by + 32, bx:bx + 32].cpu().numpy()
+            diff = np.abs(got.view(np.uint16).astype(np.int64) - want.astype(np.int64))
+            assert diff.max() <= 1, (name, bx, by, bz, diff.max())
+    del src_t, dst_t, sep_t
     torch.cuda.empty_cache()

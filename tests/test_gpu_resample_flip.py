@@ -183,6 +183,39 @@ def test_full_size_phantom_halve_and_flip(orc):
     assert torch.equal(d, s)
 
 
+def test_full_size_noise_halve_and_flip(orc):
+    """The 512^3 float32 smoothed-noise field: downscale by two (every cell
+    checked) and flips along x, y and z (sampled rows, then the in-place
+    round trip)."""
+    import torch
+    from paper_2203_10213_amd import synth, vkt
+    s = synth.smoothed_noise_f32(512, 4.0, synth.SEEDS["c2b"], device="cuda")
+    src = s.cpu().numpy()
+    got = _gpu_resample(src, (256, 256, 256), src_t=s)
+    _check_resample(orc, src, got, "noise halve", exact_half=True)
+    del got
+    g = np.random.default_rng(760)
+    d = sentinel_like(s)
+    for axis in (0, 1, 2):
+        vkt.flip(d, s, axis)
+        vkt.vktSynchronize()
+        for z, y in zip(g.integers(0, 512, 16), g.integers(0, 512, 16)):
+            row = d[z, y].cpu().numpy()
+            if axis == 0:
+                want = src[z, y, ::-1]
+            elif axis == 1:
+                want = src[z, 511 - y]
+            else:
+                want = src[511 - z, y]
+            assert np.array_equal(row.view(np.uint32), np.ascontiguousarray(want).view(np.uint32)), \
+                (axis, z, y)
+        vkt.flip(d, d, axis)  # in place back
+        vkt.vktSynchronize()
+        assert torch.equal(d.view(torch.int32), s.view(torch.int32)), axis
+    del s, d
+    torch.cuda.empty_cache()
+
+
 def test_invalid_arguments():
     import torch
     from paper_2203_10213_amd import vkt
