@@ -15,13 +15,16 @@
 //  * each input plane's halo tile is staged in LDS as FP32, double buffered,
 //    with the loads of the plane after next in flight;
 //  * x pass: the 64-wide rows of the (32 + 2r)-row halo are filtered with u
-//    into a second LDS buffer (4 outputs per thread and row, 16-byte reads);
+//    into a second LDS buffer, also double buffered (4 outputs per thread
+//    and row, 16-byte reads); one barrier per plane separates the passes;
 //  * y pass: each thread filters its 4 x 2 outputs' columns with v;
 //  * z pass: the plane's result enters an input-stationary ring of k partial
 //    sums with weights t (slots outside the slab are skipped); the oldest is
-//    a finished output.
+//    a finished output.  The z loop is unrolled by k so the ring entries
+//    stay in fixed registers.
 // The three factor vectors (16 floats each, zero padded) are brought into
-// SGPRs by one explicit scalar load per pass.
+// SGPRs by explicit scalar loads: once per tile-slab for k <= 7, else one
+// per pass.
 #include "vkt_internal.h"
 
 #include <type_traits>
@@ -155,7 +158,11 @@ __device__ __attribute__((always_inline)) inline void sep_tile(const VolDesc& a,
     const int x0 = a.rx0 + (tile % a.tiles_x) * kTX, y0 = a.ry0 + (tile / a.tiles_x) * kTY;
     const int zb = a.rz0 + slab * a.tz, ze = min(zb + a.tz, a.rz1);
     const int64_t plane = (int64_t)a.X * a.Y;
-    float* const bx = lds + 2 * G::A_CELLS;  // x-pass result
+    // x-pass results, double buffered by plane parity like the staged
+    // planes: with both double buffered, one barrier per plane suffices (the
+    // x pass of plane p + 1 writes the other buffer while slower waves still
+    // read plane p's; plane p + 2 reuses it only after the barrier of p + 1)
+    float* const bx0 = lds + 2 * G::A_CELLS;
 
     uint32_t goff[G::NE];
     int32_t loff[G::NE];
@@ -216,6 +223,7 @@ __device__ __attribute__((always_inline)) inline void sep_tile(const VolDesc& a,
         constexpr int P = decltype(U)::value;  // plane index mod K
         const int cur = (zi - zi_beg) & 1;
         const float* A = lds + cur * G::A_CELLS;
+        float* const bx = bx0 + cur * G::B_CELLS;
 
         // ---- x pass over all staged rows: bx[row][x] = sum_a u[a] A[row][x + a]
         if constexpr (!kHoist) load_factor(f, u);
@@ -310,8 +318,6 @@ __device__ __attribute__((always_inline)) inline void sep_tile(const VolDesc& a,
                 }
             }
         }
-        // the x pass of the next plane overwrites bx; its staging buffer is full
-        __syncthreads();
     };
 
     for (int zi = zi_beg; zi < zi_end; zi += K) {
@@ -325,7 +331,7 @@ template <typename T, int K>
 __global__ __launch_bounds__(kNT) void filter_sep_kernel(VolDesc a, const float* __restrict__ f,
                                                          uint32_t nblocks)
 {
-    __shared__ __align__(16) float lds[2 * GeoS<K>::A_CELLS + GeoS<K>::B_CELLS];
+    __shared__ __align__(16) float lds[2 * GeoS<K>::A_CELLS + 2 * GeoS<K>::B_CELLS];
     const uint32_t lid = xcd_remap(blockIdx.x, nblocks);
     const uint32_t ntiles = (uint32_t)a.tiles_x * (uint32_t)a.tiles_y;
     sep_tile<T, K>(a, f, (int)(lid % ntiles), (int)(lid / ntiles), lds);
