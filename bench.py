@@ -96,6 +96,7 @@ def make_cases(name, device):
 
 
 KERNEL_SOURCES = {
+    "resample": ["vkt_resample.hip", "vkt_internal.h"],
     "valu": ["vkt_filter_valu.hip", "vkt_internal.h"],
     "dot4": ["vkt_filter_dot4.hip", "vkt_internal.h"],
     "mfma": ["vkt_filter_mfma.hip", "vkt_internal.h"],
@@ -428,7 +429,8 @@ def run_transforms(args, vkt, torch):
                              hbm_frac=gbs / HBM_PEAK_GBS, algorithmic_bytes=o["bytes"]))
     dom = max((p for p in per_case if p["in_step"]), key=lambda p: p["ms"])
     roof = {"bound": "hbm", "achieved": dom["hbm_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": dom["hbm_frac"], "traffic": None, "kernel_case": dom["case"]}
+            "frac": dom["hbm_frac"], "traffic": stored_traffic(dom["case"], "resample"),
+            "kernel_case": dom["case"]}
     voxels = sum(o["voxels"] for o in step_ops)
 
     cpu = None
