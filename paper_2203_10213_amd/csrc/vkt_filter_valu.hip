@@ -20,9 +20,10 @@
 //    After the plane, the ring's oldest entry is a finished output: it is
 //    rounded, stored, and the ring advances.
 //  * Weights are uniform: they are scalar operands of the multiply-adds,
-//    loaded one group (a filter plane for k = 3, else a filter row) at a
-//    time with explicit scalar loads.  For k >= 5 the row windows stream
-//    through registers one input row at a time.
+//    loaded one group (a filter plane for k = 3, the rows (c, b), (c+1, b)
+//    for k = 5, 7, else a filter row) at a time with explicit scalar loads
+//    and one wait per group.  For k >= 5 the row windows stream through
+//    registers one input row at a time.
 //  * Single-volume launches number workgroups XCD-aware so tiles adjacent in
 //    x/y at the same z share an XCD's L2 for their halo re-reads; batched
 //    launches run persistent workgroups that take tile-slabs of many volumes
@@ -30,9 +31,15 @@
 #include "vkt_internal.h"
 
 #include <type_traits>
+#include <utility>
 
 namespace vkt {
 namespace {
+
+// Filter rows loaded per scalar wait on the row-streaming path (k = 5, 7):
+// two rows (of consecutive filter planes) measured 2 % faster than one on
+// the 512^3 5^3 workload; three spill SGPRs at k = 7.
+constexpr int kValuRowGroup = 2;
 
 constexpr int kBX = 16, kBY = 16, kNT = kBX * kBY;  // threads per workgroup
 constexpr int kVX = 4, kVY = 2;                      // outputs per thread
@@ -105,6 +112,49 @@ __device__ inline void load_weights(const Acc* p, Acc (&wv)[N])
         if constexpr (std::is_same<Acc, float>::value) wv[q] = __uint_as_float(u);
         else wv[q] = (Acc)u;
     }
+}
+
+// G filter rows of N weights, rows `stride` weights apart, issued as G
+// scalar loads followed by one wait (one wait per group of rows instead of
+// one per row).
+template <int N, int G, typename Acc>
+__device__ inline void load_weight_rows(const Acc* p, int stride, Acc (&wv)[G][N])
+{
+    static_assert(N == 8 && G >= 1 && G <= 3, "rows of 8 dwords, up to 3 per group");
+    typename SRow<8>::type r0, r1, r2;
+    const Acc* p1 = p + stride;
+    const Acc* p2 = p + 2 * stride;
+    if constexpr (G == 1)
+        asm volatile("s_load_dwordx8 %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=&s"(r0) : "s"(p));
+    else if constexpr (G == 2)
+        asm volatile("s_load_dwordx8 %0, %2, 0x0\n\ts_load_dwordx8 %1, %3, 0x0\n\t"
+                     "s_waitcnt lgkmcnt(0)"
+                     : "=&s"(r0), "=&s"(r1) : "s"(p), "s"(p1));
+    else
+        asm volatile("s_load_dwordx8 %0, %3, 0x0\n\ts_load_dwordx8 %1, %4, 0x0\n\t"
+                     "s_load_dwordx8 %2, %5, 0x0\n\ts_waitcnt lgkmcnt(0)"
+                     : "=&s"(r0), "=&s"(r1), "=&s"(r2) : "s"(p), "s"(p1), "s"(p2));
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        const uint32_t u[3] = {r0[q], G > 1 ? r1[q] : 0u, G > 2 ? r2[q] : 0u};
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if constexpr (std::is_same<Acc, float>::value) wv[g][q] = __uint_as_float(u[g]);
+            else wv[g][q] = (Acc)u[g];
+        }
+    }
+}
+
+template <typename F, int... I>
+__device__ __attribute__((always_inline)) inline void static_for_impl(
+    F& f, std::integer_sequence<int, I...>)
+{
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __attribute__((always_inline)) inline void static_for(F&& f)
+{
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
 // Dwords of a scalar load covering n weights.
@@ -271,7 +321,9 @@ __device__ void valu_tile(const VolDesc& a, const typename AccT<IACC>::type* __r
                                                      acc[c][vy][vx]);
             }
         } else {
-            // stream the row windows; one filter row live per (row, vy, c)
+            // stream the row windows; filter rows are loaded one (or, for
+            // k <= 7, a group of planes') at a time
+            constexpr int kRowGroup = K <= 7 ? kValuRowGroup : 1;
 #pragma unroll 1
             for (int jr = 0; jr < G::NROW; ++jr) {
                 Acc v[G::NR * 4];
@@ -287,6 +339,28 @@ __device__ void valu_tile(const VolDesc& a, const typename AccT<IACC>::type* __r
                 for (int vy = 0; vy < kVY; ++vy) {
                     const int b = jr - vy;
                     if (b < 0 || b >= K) continue;
+                    if constexpr (kRowGroup > 1) {
+                        // filter rows (c, b) of kRowGroup consecutive planes c
+                        // per scalar wait
+                        constexpr int NGRP = (K + kRowGroup - 1) / kRowGroup;
+                        static_for<NGRP>([&](auto gi) {
+                            constexpr int c0 = decltype(gi)::value * kRowGroup;
+                            constexpr int GN = K - c0 < kRowGroup ? K - c0 : kRowGroup;
+                            if (c0 + GN - 1 < c_lo || c0 > c_hi) return;
+                            Acc wv[GN][8];
+                            load_weight_rows<8, GN>(w + (c0 * K + b) * K, K * K, wv);
+#pragma unroll
+                            for (int g = 0; g < GN; ++g) {
+                                const int c = c0 + g;
+                                if (c < c_lo || c > c_hi) continue;
+#pragma unroll
+                                for (int aa = 0; aa < K; ++aa)
+#pragma unroll
+                                    for (int vx = 0; vx < kVX; ++vx)
+                                        acc[c][vy][vx] = mac(wv[g][aa], v[vx + aa], acc[c][vy][vx]);
+                            }
+                        });
+                    } else {
 #pragma unroll
                     for (int c = 0; c < K; ++c) {
                         if (c < c_lo || c > c_hi) continue;
@@ -298,6 +372,7 @@ __device__ void valu_tile(const VolDesc& a, const typename AccT<IACC>::type* __r
 #pragma unroll
                             for (int vx = 0; vx < kVX; ++vx)
                                 acc[c][vy][vx] = mac(wv[aa], v[vx + aa], acc[c][vy][vx]);
+                    }
                     }
                 }
             }
