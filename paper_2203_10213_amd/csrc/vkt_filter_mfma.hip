@@ -521,11 +521,13 @@ __global__ __launch_bounds__(kNT, 1) void filter_mfma_batched_kernel(BatchArgs b
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(&b.counters[0], 1u);
         __syncthreads();
-        const uint32_t it = s_item;
+        // the item index is the same in every lane: keep it (and the work item
+        // and volume descriptor it selects) in scalar registers
+        const uint32_t it = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_item);
         __syncthreads();
         if (it >= b.nitems) break;
-        const WorkItem wi = b.items[it];
-        const VolDesc a = b.vols[wi.vol];
+        const WorkItem wi = uniform_load(&b.items[it]);
+        const VolDesc a = uniform_load(&b.vols[wi.vol]);
         const uint32_t ntiles = (uint32_t)a.tiles_x * (uint32_t)a.tiles_y;
         mfma_tile<C>(a, b.wpool + a.woff, (int)(wi.lid % ntiles), (int)(wi.lid / ntiles), lds,
                      epi);

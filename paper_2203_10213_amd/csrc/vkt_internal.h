@@ -130,6 +130,23 @@ struct WorkItem {
     uint32_t lid;            // slab * tiles_x * tiles_y + tile
 };
 
+// *p as a wave-uniform value: each dword is read by every lane and taken from
+// the first, so the struct (written by the host before the launch) lives in
+// scalar registers instead of one copy per lane.
+template <typename S>
+__device__ inline S uniform_load(const S* p)
+{
+    static_assert(sizeof(S) % 4 == 0, "whole dwords");
+    constexpr int N = sizeof(S) / 4;
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(p);
+    uint32_t tmp[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) tmp[i] = (uint32_t)__builtin_amdgcn_readfirstlane((int)src[i]);
+    S out;
+    __builtin_memcpy(&out, tmp, sizeof(S));
+    return out;
+}
+
 // Arguments of a batched persistent kernel (one arithmetic class).
 struct BatchArgs {
     const VolDesc* vols;
