@@ -26,8 +26,9 @@
 // The four x-strips a wave owns are adjacent, so one 32-byte LDS read per
 // (row block, K chunk, operand piece) holds all four strips' 16-byte windows
 // (at dword offsets 0..3).  The finished column group of all of a wave's
-// tiles is an 8 x 64 block of outputs; it is transposed through LDS so that
-// each lane rounds and stores one row of 8 cells with one vector store.
+// tiles is an 8 x 32 (16x16 tiles) or 8 x 64 (32x32) block of outputs; it is
+// transposed through LDS so that each lane rounds and stores 4 or 8 cells of
+// one row with one vector store.
 //
 // Split precision (16-bit operands, exact FP32 products, FP32 sums):
 //   uint8   voxels: exact in fp16 (1 piece) x weights in 2 fp16 pieces;
@@ -110,8 +111,11 @@ struct Cfg {
     static constexpr int SX = 16;                                   // strips per workgroup
     static constexpr int WS = 4;                                    // strips per wave
     static_assert(SX == 4 * WS, "four waves");
-    static constexpr int SY = SHAPE == 16 ? 4 : 2;                  // row blocks per workgroup
-    static constexpr int TX = SX * NX, TY = SY * M::MT;             // 32 x 64 output tile
+    // row blocks per workgroup: 2 for both shapes (16x16 tiles with 4 row
+    // blocks needed a third more registers, two waves per SIMD instead of
+    // three or four, and measured 5-8 % slower)
+    static constexpr int SY = 2;
+    static constexpr int TX = SX * NX, TY = SY * M::MT;             // 32 x 32 or 32 x 64 tile
     // a lane's 8-column windows of the wave's WS strips span SEGN columns,
     // read as NRD 16-byte pieces
     static constexpr int SEGN = NX * (WS - 1) + 8;
@@ -244,15 +248,17 @@ template <typename T, int N>
 __device__ inline void store_row(__amdgpu_buffer_rsrc_t r, uint32_t off, const float (&v)[N],
                                  bool vec, int nx, float unscale)
 {
-    static_assert(N == 8, "8 cells per row");
+    static_assert(N == 8 || N == 4, "rows of 8 or 4 cells");
     if constexpr (std::is_same<T, float>::value) {
         uint32_t u[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) u[i] = __float_as_uint(v[i] * unscale);
         if (vec) {
-            __builtin_amdgcn_raw_buffer_store_b128(u32x4{u[0], u[1], u[2], u[3]}, r, (int)off, 0, 0);
-            __builtin_amdgcn_raw_buffer_store_b128(u32x4{u[4], u[5], u[6], u[7]}, r, (int)off + 16,
-                                                   0, 0);
+#pragma unroll
+            for (int h = 0; h < N / 4; ++h)
+                __builtin_amdgcn_raw_buffer_store_b128(
+                    u32x4{u[4 * h], u[4 * h + 1], u[4 * h + 2], u[4 * h + 3]}, r, (int)off + 16 * h,
+                    0, 0);
         } else {
 #pragma unroll
             for (int i = 0; i < N; ++i)
@@ -267,17 +273,23 @@ __device__ inline void store_row(__amdgpu_buffer_rsrc_t r, uint32_t off, const f
             // floor(q + 1/2) saturated: truncation of a value clamped to [0, max]
             u[i] = (uint32_t)__builtin_amdgcn_fmed3f(fmaf(v[i], unscale, 0.5f), 0.f, kMax);
         if (vec) {
-            if constexpr (sizeof(T) == 2) {
+            typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+            if constexpr (sizeof(T) == 2 && N == 8) {
                 __builtin_amdgcn_raw_buffer_store_b128(
                     u32x4{u[0] | (u[1] << 16), u[2] | (u[3] << 16), u[4] | (u[5] << 16),
                           u[6] | (u[7] << 16)},
                     r, (int)off, 0, 0);
-            } else {
-                typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+            } else if constexpr (sizeof(T) == 2) {
+                __builtin_amdgcn_raw_buffer_store_b64(
+                    u32x2{u[0] | (u[1] << 16), u[2] | (u[3] << 16)}, r, (int)off, 0, 0);
+            } else if constexpr (N == 8) {
                 __builtin_amdgcn_raw_buffer_store_b64(
                     u32x2{u[0] | (u[1] << 8) | (u[2] << 16) | (u[3] << 24),
                           u[4] | (u[5] << 8) | (u[6] << 16) | (u[7] << 24)},
                     r, (int)off, 0, 0);
+            } else {
+                __builtin_amdgcn_raw_buffer_store_b32(u[0] | (u[1] << 8) | (u[2] << 16) | (u[3] << 24),
+                                                      r, (int)off, 0, 0);
             }
         } else {
 #pragma unroll
@@ -371,19 +383,23 @@ __device__ void mfma_tile(const VolDesc& a, const float* __restrict__ w, int til
     };
 
     // ---- output block of the wave: its finished columns form an 8 (x) by
-    // 64 (y) block; lanes holding a finished column write it to the wave's
-    // LDS block (y fastest), then lane l reads row l and stores its 8 cells
+    // BY = SY * MT (32 or 64) (y) block; lanes holding a finished column write
+    // it to the wave's LDS block (y fastest), then each lane reads its share of
+    // one row (8 cells, or 4 of a 32-row block) and stores it
     constexpr int BX = C::WS * C::NX, BY = C::SY * M::MT;
-    static_assert(BX == 8 && BY == 64, "one output row of 8 cells per lane");
+    static_assert(BX == 8 && (BY == 64 || BY == 32), "8 x 64 or 8 x 32 output blocks");
+    // lane l stores CPL cells of row l % BY (for 32 rows, two lanes per row)
+    constexpr int CPL = BX * BY / 64;
     const int jcol = lane % M::NT, gq = lane / M::NT;
     const int xo = jcol - (K - 1) * C::NX;  // finished column group k-1
     const bool fin = xo >= 0 && xo < C::NX;
     float* const blk = epi + wave * BX * BY;
-    const int xw = x0 + BX * wave, yl = y0 + lane;
+    const int lrow = lane % BY, lpart = lane / BY;
+    const int xw = x0 + BX * wave + CPL * lpart, yl = y0 + lrow;
     // rows past the volume's last row fall beyond the plane: dropped
     const uint32_t ooff =
         yl < a.ry1 ? ((uint32_t)yl * (uint32_t)a.X + (uint32_t)xw) * (uint32_t)sizeof(T) : kOutside;
-    const bool vec_row = a.vec_ok && xw + BX <= a.rx1;
+    const bool vec_row = a.vec_ok && xw + CPL <= a.rx1;
 
     acc_t acc[C::MTW];
 #pragma unroll
@@ -472,13 +488,13 @@ __device__ void mfma_tile(const VolDesc& a, const float* __restrict__ w, int til
             }
             // the wave's own LDS writes complete before its lanes read them
             asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-            float v[BX];
+            float v[CPL];
 #pragma unroll
-            for (int xl = 0; xl < BX; ++xl) v[xl] = blk[xl * BY + lane];
+            for (int xl = 0; xl < CPL; ++xl) v[xl] = blk[(CPL * lpart + xl) * BY + lrow];
             const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(
                 static_cast<char*>(a.dst) + (int64_t)zo * plane_bytes, (short)0, plane_bytes,
                 (int)kRsrcWord3);
-            store_row<T, BX>(rd, ooff, v, vec_row, a.rx1 - xw, a.unscale);
+            store_row<T, CPL>(rd, ooff, v, vec_row, a.rx1 - xw, a.unscale);
             asm volatile("" ::: "memory");
         }
         // ---- advance the ring
@@ -495,7 +511,8 @@ constexpr int lds_elems()
 {
     return 2 * C::PC::PS * C::HY * C::PITCH;
 }
-// output transposition blocks: 4 waves x 8 x 64 floats
+// output transposition blocks: 4 waves x 8 x 64 floats (the 32-row blocks of
+// 16x16 tiles use half)
 constexpr int kEpiFloats = 4 * 8 * 64;
 
 template <class C>
