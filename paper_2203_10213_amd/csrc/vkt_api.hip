@@ -484,7 +484,10 @@ const void* mfma_batched_kernel(vktDataFormat f, int k, bool six_products)
                   : mfma_batched_kernel_s32(f, k, six_products);
 }
 
-ClassGeom mfma_geom(int k) { return k <= 7 ? mfma_geom_s16(k) : mfma_geom_s32(k); }
+ClassGeom mfma_geom(vktDataFormat f, int k, bool six_products)
+{
+    return k <= 7 ? mfma_geom_s16(f, k, six_products) : mfma_geom_s32(f, k, six_products);
+}
 
 int resident_wgs(const void* func)
 {

@@ -51,7 +51,7 @@ const void* class_kernel(const ClassKey& c)
 ClassGeom class_geom(const ClassKey& c)
 {
     if (c.path == 2) return dot4_geom(c.k);
-    return c.path ? mfma_geom(c.k) : valu_geom(c.k);
+    return c.path ? mfma_geom((vktDataFormat)c.fmt, c.k, c.flag != 0) : valu_geom(c.k);
 }
 
 // Weights per filter in the class's pools: k^3 (float and int pools), or the

@@ -114,7 +114,12 @@ struct Cfg {
     // row blocks per workgroup: 2 for both shapes (16x16 tiles with 4 row
     // blocks needed a third more registers, two waves per SIMD instead of
     // three or four, and measured 5-8 % slower)
-    static constexpr int SY = 2;
+    // (32x32 tiles: one row block where that brings the kernel down to two
+    // waves per SIMD -- 9^3 with uint8 or 3-product float32 operands, 21 %
+    // faster on the 1024^3 9^3 workload; elsewhere it stays at one wave and
+    // the taller tile measured faster)
+    static constexpr int SY =
+        SHAPE == 16 ? 2 : (K == 9 && (PM == kU8 || PM == kF32x3) ? 1 : 2);
     static constexpr int TX = SX * NX, TY = SY * M::MT;             // 32 x 32 or 32 x 64 tile
     // a lane's 8-column windows of the wave's WS strips span SEGN columns,
     // read as NRD 16-byte pieces
@@ -566,20 +571,20 @@ __global__ __launch_bounds__(kNT, 1) void filter_mfma_batched_kernel(BatchArgs b
 #define VKT_MFMA_FN(name) name##_s32
 #endif
 
-ClassGeom geom_here(int k)
+template <class C>
+ClassGeom geom_of()
 {
-    using C = Cfg<float, VKT_MFMA_SHAPE == 16 ? 5 : 9, kF32x3>;
     ClassGeom g;
     g.tx = C::TX;
     g.ty = C::TY;
-    g.tz_min = 4 * k;
+    g.tz_min = 4 * (2 * C::R + 1);
     return g;
 }
 
 template <class C>
 hipError_t launch_cfg(const FilterJob& j, hipStream_t s)
 {
-    const ClassGeom g = geom_here(j.k);
+    const ClassGeom g = geom_of<C>();
     // the output region's tiles and z extent (the whole volume unless a range)
     const int RX = j.roi[3] - j.roi[0], RY = j.roi[4] - j.roi[1], RZ = j.roi[5] - j.roi[2];
     const int64_t ntiles = (int64_t)((RX + g.tx - 1) / g.tx) * ((RY + g.ty - 1) / g.ty);
@@ -606,6 +611,16 @@ hipError_t dispatch_k(const FilterJob& j, hipStream_t s)
 }
 
 template <typename T, int PM>
+ClassGeom geom_k(int k)
+{
+#define VKT_CASE(KK) \
+    case KK: return geom_of<Cfg<T, KK, PM>>();
+    switch (k) { VKT_MFMA_KS(VKT_CASE) }
+#undef VKT_CASE
+    return ClassGeom{};
+}
+
+template <typename T, int PM>
 const void* batched_k(int k)
 {
 #define VKT_CASE(KK) \
@@ -617,7 +632,16 @@ const void* batched_k(int k)
 
 }  // namespace
 
-ClassGeom VKT_MFMA_FN(mfma_geom)(int k) { return geom_here(k); }
+ClassGeom VKT_MFMA_FN(mfma_geom)(vktDataFormat f, int k, bool six_products)
+{
+    switch (f) {
+    case vktDataFormatUInt8: return geom_k<uint8_t, kU8>(k);
+    case vktDataFormatUInt16: return geom_k<uint16_t, kU16>(k);
+    case vktDataFormatFloat32:
+        return six_products ? geom_k<float, kF32x6>(k) : geom_k<float, kF32x3>(k);
+    }
+    return ClassGeom{};
+}
 
 hipError_t VKT_MFMA_FN(launch_filter_mfma)(const FilterJob& j, bool six_products, hipStream_t s)
 {

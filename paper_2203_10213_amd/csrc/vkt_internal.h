@@ -195,8 +195,8 @@ hipError_t launch_filter_mfma_s16(const FilterJob& j, bool six_products, hipStre
 hipError_t launch_filter_mfma_s32(const FilterJob& j, bool six_products, hipStream_t s);
 const void* mfma_batched_kernel_s16(vktDataFormat f, int k, bool six_products);
 const void* mfma_batched_kernel_s32(vktDataFormat f, int k, bool six_products);
-ClassGeom mfma_geom_s16(int k);
-ClassGeom mfma_geom_s32(int k);
+ClassGeom mfma_geom_s16(vktDataFormat f, int k, bool six_products);
+ClassGeom mfma_geom_s32(vktDataFormat f, int k, bool six_products);
 
 // Batched persistent kernels: the kernel function of a class (for launches
 // and graph kernel nodes, taking one BatchArgs by value), its geometry, and
@@ -204,7 +204,7 @@ ClassGeom mfma_geom_s32(int k);
 const void* valu_batched_kernel(vktDataFormat f, int k, bool int_acc);
 ClassGeom valu_geom(int k);
 const void* mfma_batched_kernel(vktDataFormat f, int k, bool six_products);
-ClassGeom mfma_geom(int k);
+ClassGeom mfma_geom(vktDataFormat f, int k, bool six_products);
 // Fill in the descriptor fields the kernels derive from a FilterJob.
 VolDesc make_desc(const FilterJob& j, int tz, ClassGeom g);
 // Workgroups of 256 threads of `func` resident on the whole current device
