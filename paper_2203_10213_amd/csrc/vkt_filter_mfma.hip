@@ -131,6 +131,12 @@ struct Cfg {
     static constexpr int HY = TY + K - 1;                           // staged rows
     static constexpr int NE = (PITCH * HY + kNT - 1) / kNT;         // staged cells / thread
     static constexpr int MTW = WS * SY;                             // M tiles per wave
+    // waves per SIMD the single-volume kernel is compiled for: 16x16 tiles
+    // with uint8 or 3-product float32 operands fit 128 registers (four
+    // waves) without spills; uint16 and 6-product float32 would spill there
+    // and keep three; 32x32 tiles take what they need (one or two)
+    static constexpr int WAVES =
+        SHAPE == 16 ? (PM == kU8 || PM == kF32x3 ? 4 : 3) : 1;
 };
 
 __device__ inline int addr_map(int64_t i, int64_t n, int mode)
@@ -521,7 +527,8 @@ constexpr int lds_elems()
 constexpr int kEpiFloats = 4 * 8 * 64;
 
 template <class C>
-__global__ __launch_bounds__(kNT, 1) void filter_mfma_kernel(VolDesc a,
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(C::WAVES)))
+void filter_mfma_kernel(VolDesc a,
                                                              const float* __restrict__ w,
                                                              uint32_t nblocks)
 {
