@@ -137,6 +137,9 @@ struct Cfg {
     // and keep three; 32x32 tiles take what they need (one or two)
     static constexpr int WAVES =
         SHAPE == 16 ? (PM == kU8 || PM == kF32x3 ? 4 : 3) : 1;
+    // the persistent batched kernels need more registers: three waves for
+    // the 16-bit operand classes, the float32 classes as they come
+    static constexpr int BWAVES = SHAPE == 16 && (PM == kU8 || PM == kU16) ? 3 : 1;
 };
 
 __device__ inline int addr_map(int64_t i, int64_t n, int mode)
@@ -542,7 +545,8 @@ void filter_mfma_kernel(VolDesc a,
 // Persistent workgroups over a queue of (volume, tile-slab) items; the last
 // workgroup to finish resets the queue counters.
 template <class C>
-__global__ __launch_bounds__(kNT, 1) void filter_mfma_batched_kernel(BatchArgs b)
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(C::BWAVES)))
+void filter_mfma_batched_kernel(BatchArgs b)
 {
     __shared__ __align__(16) uint16_t lds[lds_elems<C>()];
     __shared__ __align__(16) float epi[kEpiFloats];
