@@ -31,6 +31,7 @@ BF16_MFMA_PEAK_TF = 2500.0     # MI355X dense bf16 matrix, TFLOP/s
 # 8-bit dot products on the vector ALUs: 256 CUs x 4 SIMDs x 16 lanes x 4 MACs
 # x 2 ops x 2.4 GHz (v_dot4 issues at the full VALU rate)
 INT8_DOT_PEAK_TOPS = 256 * 4 * 16 * 4 * 2 * 2.4e9 / 1e12
+INT8_MFMA_PEAK_TOPS = 5000.0   # MI355X dense int8 matrix, TOP/s
 
 
 def parse():
@@ -46,6 +47,9 @@ def parse():
                     help="default: fp32 for c1/c2 (the plain-path configurations), "
                          "auto (split bf16/fp16 matrix path for k >= 5) otherwise")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--int8-matrix", action="store_true",
+                    help="uint8 3^3 integer filters on the int8 matrix cores instead of "
+                         "the 8-bit dot products (vktSetInt8Matrix(1))")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--separable", action="store_true",
@@ -99,6 +103,7 @@ KERNEL_SOURCES = {
     "resample": ["vkt_resample.hip", "vkt_internal.h"],
     "valu": ["vkt_filter_valu.hip", "vkt_internal.h"],
     "dot4": ["vkt_filter_dot4.hip", "vkt_internal.h"],
+    "i8mma": ["vkt_filter_i8mma.hip", "vkt_internal.h"],
     "mfma": ["vkt_filter_mfma.hip", "vkt_internal.h"],
 }
 
@@ -139,6 +144,8 @@ def arith_dtype(c, precision):
         return "f16x2->f32"
     if c["path"] == "dot4":
         return "u8dot4->i32"
+    if c["path"] == "i8mma":
+        return "i8mma->i32"
     if c["path"] == "sep":
         return "f32(rank-1)"
     if c["D"] is not None:
@@ -146,18 +153,25 @@ def arith_dtype(c, precision):
     return "f32"
 
 
-def kernel_path(c, precision, separable=False):
+def kernel_path(c, precision, separable=False, int8_matrix=False):
     """The library's plan rule: float-weight filters with k >= 5 run on the
     matrix cores unless the precision is fp32; uint8 volumes with integer
     filters of k <= 7, weights all in [0, 255] or all in [-128, 127],
     sum |w| <= 2048, divisor <= 2^19 and rows of a multiple of 4 cells run as
-    8-bit dot products; the rest on the vector ALUs in FP32 / int32."""
+    8-bit dot products (k = 3 with weights in [-128, 127] as int8 products on
+    the matrix cores when that is turned on); the rest on the vector ALUs in
+    FP32 / int32."""
     import numpy as np
     if separable and rank1(c["w"]) and not (c["k"] <= 3 and dot4_ok(c)):
         return "sep"
     if c["D"] is None:
         return "mfma" if (c["k"] >= 5 and precision != "fp32") else "valu"
-    return "dot4" if dot4_ok(c) else "valu"
+    if not dot4_ok(c):
+        return "valu"
+    w = np.asarray(c["w"], np.int64)
+    if int8_matrix and c["k"] == 3 and w.min() >= -128 and w.max() <= 127:
+        return "i8mma"
+    return "dot4"
 
 
 def dot4_ok(c):
@@ -204,13 +218,15 @@ def case_roofline(c, ms):
     flops = c["voxels"] * (6 * c["k"] if c.get("path") == "sep" else c["flops_per_voxel"])
     gbs = bytes_alg / t / 1e9
     tfs = flops / t / 1e12
-    peak_c = {"mfma": BF16_MFMA_PEAK_TF, "dot4": INT8_DOT_PEAK_TOPS}.get(c["path"], FP32_VECTOR_PEAK_TF)
+    peak_c = {"mfma": BF16_MFMA_PEAK_TF, "dot4": INT8_DOT_PEAK_TOPS,
+              "i8mma": INT8_MFMA_PEAK_TOPS}.get(c["path"], FP32_VECTOR_PEAK_TF)
     if bytes_alg / (HBM_PEAK_GBS * 1e9) >= flops / (peak_c * 1e12):
         roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": gbs / HBM_PEAK_GBS}
     else:
-        roof = {"bound": "mfma" if c["path"] == "mfma" else "alu", "achieved": tfs,
-                "peak": peak_c, "unit": "TOP/s" if c["path"] == "dot4" else "TFLOP/s",
+        roof = {"bound": "mfma" if c["path"] in ("mfma", "i8mma") else "alu", "achieved": tfs,
+                "peak": peak_c,
+                "unit": "TOP/s" if c["path"] in ("dot4", "i8mma") else "TFLOP/s",
                 "frac": tfs / peak_c}
     return dict(case=c["name"], path=c["path"], ms=ms,
                 gvoxels_s=c["voxels"] / t / 1e9, hbm_gbs=gbs, hbm_frac=gbs / HBM_PEAK_GBS,
@@ -489,6 +505,7 @@ def main():
     vkt.vktSetStream(stream)
     vkt.vktSetPrecision(args.precision)
     vkt.vktSetSeparable(args.separable)
+    vkt.vktSetInt8Matrix(args.int8_matrix)
     if args.workload == "c4":
         print(json.dumps(run_batched(args, vkt, torch)))
         return
@@ -498,7 +515,7 @@ def main():
     print(f"[bench] building inputs for {args.workload}", file=sys.stderr, flush=True)
     cases = make_cases(args.workload, dev)
     for c in cases:
-        c["path"] = kernel_path(c, args.precision, args.separable)
+        c["path"] = kernel_path(c, args.precision, args.separable, args.int8_matrix)
         c["dst"] = torch.empty_like(c["src"])
         c["hs"] = vkt.volume_from_tensor(c["src"])
         c["hd"] = vkt.volume_from_tensor(c["dst"])

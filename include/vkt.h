@@ -298,6 +298,18 @@ vktError vktSetAutotune(int enable);
  * always runs the dense arithmetic. */
 vktError vktSetSeparable(int enable);
 vktError vktGetSeparable(int* enable);
+/* Exact int8 matrix-core path (opt-in, per thread; default: the
+ * VKT_INT8_MATRIX environment variable, "1" enables).  UInt8 volumes filtered with a
+ * 3x3x3 integer filter whose weights all lie in [-128, 127] (sum |w| <= 2048,
+ * divisor <= 2^19, rows a multiple of 4 cells, 4-byte aligned buffers, and
+ * for a range x bounds that are multiples of 4) run as int8 x int8 products
+ * with int32 sums on the matrix cores; otherwise they run as 8-bit dot
+ * products on the vector ALUs (measured faster on the 512^3 box filter).  Both compute the exact integer sum, so the stored
+ * results are identical.  Single-volume calls only (ApplyFilter and
+ * ApplyFilterRange); the batched form uses the dot products. */
+vktError vktSetInt8Matrix(int enable);
+vktError vktGetInt8Matrix(int* enable);
+
 /* *separable = 1 if the filter's weights are rank 1 (as above), else 0. */
 vktError vktFilterIsSeparable(vktFilter filter, int* separable);
 

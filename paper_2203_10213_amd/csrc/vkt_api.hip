@@ -22,6 +22,7 @@ struct ThreadState {
     vktPrecision precision = vktPrecisionAuto;
     bool autotune = false;
     bool separable = false;
+    bool int8_matrix = false;
     bool init = false;
 };
 thread_local ThreadState t_state;
@@ -37,6 +38,7 @@ ThreadState& state()
         }
         if (const char* p = std::getenv("VKT_AUTOTUNE")) t_state.autotune = p[0] == '1';
         if (const char* p = std::getenv("VKT_SEPARABLE")) t_state.separable = p[0] == '1';
+        if (const char* p = std::getenv("VKT_INT8_MATRIX")) t_state.int8_matrix = p[0] == '1';
     }
     return t_state;
 }
@@ -260,6 +262,40 @@ vktError create_filter(vktFilter* out, int32_t k, const float* wf, const int32_t
         if (e == hipSuccess)
             e = hipMemcpy(dwq, hq.data(), hq.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
     }
+    // int8 matrix-core operands (k = 3, signed 8-bit weights, the same bounds
+    // as the dot products): for filter plane c and lane l (m = l mod 16,
+    // K chunk g = l / 16), byte i of W_c pairs with byte i of the lane's
+    // staged-cell chunk: g < 3 holds input row b = g, columns x0t + i, so the
+    // tap is a = i - m + 1; chunk 3 holds the cells left (byte 2b, tap 0 of
+    // output m = 0) and right (byte 2b + 1, tap 2 of m = 15) of row b
+    uint32_t* dwm = nullptr;
+    bool m8_ok = false;
+    if (e == hipSuccess && wi && k == 3 && sum_abs <= 2048 && divisor <= (1 << 19)) {
+        m8_ok = true;
+        for (int i = 0; i < n; ++i) m8_ok = m8_ok && hi[i] >= -128 && hi[i] <= 127;
+    }
+    if (e == hipSuccess && m8_ok) {
+        std::vector<uint8_t> hm(vkt::kI8mmaTableBytes, 0);
+        auto wk = [&](int c, int b, int a) { return (uint8_t)(int8_t)hi[(size_t)a + 3 * (b + 3 * c)]; };
+        for (int c = 0; c < 3; ++c)
+            for (int l = 0; l < 64; ++l) {
+                const int m = l % 16, g = l / 16;
+                uint8_t* row = &hm[(size_t)(c * 64 + l) * 16];
+                if (g < 3) {
+                    for (int i = 0; i < 16; ++i) {
+                        const int a = i - m + 1;
+                        if (a >= 0 && a < 3) row[i] = wk(c, g, a);
+                    }
+                } else {
+                    for (int b = 0; b < 3; ++b) {
+                        if (m == 0) row[2 * b] = wk(c, b, 0);
+                        if (m == 15) row[2 * b + 1] = wk(c, b, 2);
+                    }
+                }
+            }
+        e = hipMalloc(&dwm, hm.size());
+        if (e == hipSuccess) e = hipMemcpy(dwm, hm.data(), hm.size(), hipMemcpyHostToDevice);
+    }
     // rank-1 factors for the separable path
     float* dsep = nullptr;
     Rank1 r1;
@@ -290,6 +326,7 @@ vktError create_filter(vktFilter* out, int32_t k, const float* wf, const int32_t
         if (dwf) (void)hipFree(dwf);
         if (dwi) (void)hipFree(dwi);
         if (dwq) (void)hipFree(dwq);
+        if (dwm) (void)hipFree(dwm);
         if (dsep) (void)hipFree(dsep);
         return from_hip(e);
     }
@@ -304,11 +341,13 @@ vktError create_filter(vktFilter* out, int32_t k, const float* wf, const int32_t
     }
     auto* f = new (std::nothrow) vktFilter_{k, wi != nullptr, wi ? divisor : 1, sum_abs,
                                             wscale, 0, dwf, dwi, dwq, q_ok, q_signed,
-                                            sum_int, r1.ok, sep_sum_abs, dsep, device};
+                                            sum_int, m8_ok, dwm, r1.ok, sep_sum_abs, dsep,
+                                            device};
     if (!f) {
         (void)hipFree(dwf);
         if (dwi) (void)hipFree(dwi);
         if (dwq) (void)hipFree(dwq);
+        if (dwm) (void)hipFree(dwm);
         if (dsep) (void)hipFree(dsep);
         return vktOutOfMemory;
     }
@@ -348,6 +387,7 @@ hipStream_t thread_stream() { return state().stream; }
 vktPrecision thread_precision() { return state().precision; }
 bool thread_autotune() { return state().autotune; }
 bool thread_separable() { return state().separable; }
+bool thread_int8_matrix() { return state().int8_matrix; }
 
 VolDesc make_desc(const FilterJob& j, int tz, ClassGeom g)
 {
@@ -464,6 +504,11 @@ vktError build_job(const vktStructuredVolume_* dst, const vktStructuredVolume_* 
         // weights add the 128 * sum(w) the cells lost by entering as s - 128
         const double D = (double)filt->divisor;
         j.q_bias = (float)(0.25 / D + (filt->q_signed ? 128.0 * (double)filt->sum_int / D : 0.0));
+        // k = 3 with signed 8-bit weights: exact int8 products on the matrix
+        // cores (cells always enter as s - 128) when the thread enables them
+        j.i8mma = filt->m8_ok && state().int8_matrix;
+        j.wm = filt->d_wm;
+        j.m8_bias = (float)(0.25 / D + 128.0 * (double)filt->sum_int / D);
     }
     // float32 cells: the 6-product split keeps every product term down to
     // 2^-16 relative (about 1e-7 after rounding); Auto uses it.  The 3-product
@@ -622,7 +667,7 @@ vktError vktFilterDestroy(vktFilter f)
         if (!f || !g_filters.erase(f)) return vktInvalidValue;
     }
     hipError_t e = hipFree(f->d_wf);
-    for (void* p : {(void*)f->d_wi, (void*)f->d_wq, (void*)f->d_sep}) {
+    for (void* p : {(void*)f->d_wi, (void*)f->d_wq, (void*)f->d_wm, (void*)f->d_sep}) {
         if (!p) continue;
         hipError_t e2 = hipFree(p);
         if (e == hipSuccess) e = e2;
@@ -667,6 +712,7 @@ vktError vktApplyFilter(vktStructuredVolume dst, vktStructuredVolume src, vktFil
     if (e != vktNoError) return e;
     if (j.sep) return from_hip(vkt::launch_filter_sep(j, state().stream));
     if (mfma) return from_hip(vkt::launch_filter_mfma(j, six, state().stream));
+    if (j.i8mma) return from_hip(vkt::launch_filter_i8mma(j, state().stream));
     if (j.dot4) return from_hip(vkt::launch_filter_dot4(j, state().stream));
     return from_hip(vkt::launch_filter_valu(j, state().stream));
 }
@@ -687,6 +733,7 @@ vktError vktApplyFilterRange(vktStructuredVolume dst, vktStructuredVolume src, v
     if (x0 == x1 || y0 == y1 || z0 == z1) return vktNoError;  // empty region
     if (j.sep) return from_hip(vkt::launch_filter_sep(j, state().stream));
     if (mfma) return from_hip(vkt::launch_filter_mfma(j, six, state().stream));
+    if (j.i8mma) return from_hip(vkt::launch_filter_i8mma(j, state().stream));
     if (j.dot4) return from_hip(vkt::launch_filter_dot4(j, state().stream));
     return from_hip(vkt::launch_filter_valu(j, state().stream));
 }
@@ -737,6 +784,19 @@ vktError vktGetSeparable(int* enable)
 {
     if (!enable) return vktInvalidValue;
     *enable = state().separable ? 1 : 0;
+    return vktNoError;
+}
+
+vktError vktSetInt8Matrix(int enable)
+{
+    state().int8_matrix = enable != 0;
+    return vktNoError;
+}
+
+vktError vktGetInt8Matrix(int* enable)
+{
+    if (!enable) return vktInvalidValue;
+    *enable = state().int8_matrix ? 1 : 0;
     return vktNoError;
 }
 

@@ -34,6 +34,10 @@ struct vktFilter_ {
     uint32_t* d_wq;
     bool q_ok, q_signed;
     int64_t sum_int;            // sum w for integer filters
+    // int8 matrix-core operands (k = 3, weights in [-128, 127]): per filter
+    // plane c the x-Toeplitz W_c as 64 lanes x 16 signed bytes
+    bool m8_ok;
+    uint32_t* d_wm;
     // rank-1 factors (u over x | v over y | t over z, 16 floats each) with
     // u (x) v (x) t = w (exactly, with integer factors, for integer filters)
     bool sep_ok;
@@ -89,6 +93,9 @@ struct FilterJob {
     bool q_signed;           // signed 8-bit weights (cells enter as s - 128)
     const uint32_t* wq;      // device packed weights
     float q_bias;            // epilogue constant of the dot-product path
+    bool i8mma;              // uint8 cells, k = 3, int8 matrix-core path
+    const uint32_t* wm;      // device W operands of that path
+    float m8_bias;           // its epilogue constant: (1/4 + 128 sum(w)) / D
     bool sep;                // rank-1 filter on the separable path
     const float* wsep;       // device factors u | v | t (16 floats each)
 };
@@ -183,6 +190,12 @@ hipError_t launch_filter_sep(const FilterJob& j, hipStream_t s);
 hipError_t launch_filter_dot4(const FilterJob& j, hipStream_t s);
 const void* dot4_batched_kernel(int k, bool q_signed);
 ClassGeom dot4_geom(int k);
+// Exact int8 matrix-core path for uint8 volumes with 3x3x3 filters of signed
+// 8-bit weights (single-volume launches).
+hipError_t launch_filter_i8mma(const FilterJob& j, hipStream_t s);
+ClassGeom i8mma_geom();
+// Bytes of the W operand table of that path (3 filter planes x 64 lanes x 16).
+constexpr int kI8mmaTableBytes = 3 * 64 * 16;
 // Dwords of packed weights per filter on the dot-product path.
 inline int dot4_words(int k) { return k * k * ((k + 3) / 4); }
 // Matrix-core path for float-weight filters with k >= 5.  six_products
@@ -231,5 +244,6 @@ hipStream_t thread_stream();
 vktPrecision thread_precision();
 bool thread_autotune();
 bool thread_separable();
+bool thread_int8_matrix();
 
 }  // namespace vkt

@@ -62,6 +62,8 @@ SIGNATURES = {
     "vktSetAutotune": [ctypes.c_int],
     "vktSetSeparable": [ctypes.c_int],
     "vktGetSeparable": [ctypes.POINTER(ctypes.c_int)],
+    "vktSetInt8Matrix": [ctypes.c_int],
+    "vktGetInt8Matrix": [ctypes.POINTER(ctypes.c_int)],
     "vktFilterIsSeparable": [_P, ctypes.POINTER(ctypes.c_int)],
     "vktSetStream": [_P],
     "vktGetStream": [_PP],
@@ -306,6 +308,16 @@ def vktSetSeparable(enable):
 def vktGetSeparable():
     v = ctypes.c_int()
     _ok(lib().vktGetSeparable(ctypes.byref(v)), "vktGetSeparable")
+    return bool(v.value)
+
+
+def vktSetInt8Matrix(enable):
+    _ok(lib().vktSetInt8Matrix(1 if enable else 0), "vktSetInt8Matrix")
+
+
+def vktGetInt8Matrix():
+    v = ctypes.c_int()
+    _ok(lib().vktGetInt8Matrix(ctypes.byref(v)), "vktGetInt8Matrix")
     return bool(v.value)
 
 

@@ -69,6 +69,8 @@ def test_null_handles_rejected_without_gpu(vkt):
     assert L.vktStructuredVolumeCreate(None, 4, 4, 4, 0, 1, 1, 1, 0, 1) == vkt.vktInvalidValue
     assert L.vktStructuredVolumeCreateFromDevicePtr(None, 4, 4, 4, 0, None, 0, 1) \
         == vkt.vktInvalidValue
+    assert L.vktGetInt8Matrix(None) == vkt.vktInvalidValue
+    assert L.vktGetSeparable(None) == vkt.vktInvalidValue
 
 
 def test_filter_validation_without_gpu(vkt):
@@ -104,6 +106,22 @@ def test_precision_is_thread_local(vkt):
     assert vkt.vktGetPrecision() == vkt.vktPrecisionSplitBF16
     assert vkt.lib().vktSetPrecision(7) == vkt.vktInvalidValue
     vkt.vktSetPrecision("auto")
+
+
+def test_int8_matrix_switch_is_thread_local(vkt):
+    assert vkt.vktGetInt8Matrix() is False  # opt-in
+    vkt.vktSetInt8Matrix(True)
+    seen = {}
+
+    def other():
+        seen["p"] = vkt.vktGetInt8Matrix()
+
+    th = threading.Thread(target=other)
+    th.start()
+    th.join()
+    assert seen == {"p": False}
+    assert vkt.vktGetInt8Matrix() is True
+    vkt.vktSetInt8Matrix(False)
 
 
 def test_stream_is_thread_local(vkt):
