@@ -15,7 +15,7 @@ import numpy as np
 
 from ._build import LIB, build_oracle
 
-__all__ = ["MODES", "correlate", "correlate_points", "store_float_filter",
+__all__ = ["MODES", "correlate", "correlate_box", "correlate_points", "store_float_filter",
            "store_int_filter", "apply_filter", "fill_raw", "fill_range",
            "address", "resample", "flip", "brick_grid", "brick_decompose", "lib"]
 
@@ -39,6 +39,9 @@ def lib():
     L.vkto_address.restype = i64
     L.vkto_correlate.argtypes = [vp, ctypes.c_int, i64, i64, i64, ctypes.c_int,
                                  dp, ctypes.c_int, i64, i64, dp, dp, ctypes.c_int]
+    L.vkto_correlate_box.argtypes = [vp, ctypes.c_int, i64, i64, i64, ctypes.c_int,
+                                     dp, ctypes.c_int, i64, i64, i64, i64, i64, i64,
+                                     dp, dp, ctypes.c_int]
     L.vkto_correlate_points.argtypes = [vp, ctypes.c_int, i64, i64, i64,
                                         ctypes.c_int, dp, ctypes.c_int,
                                         ctypes.POINTER(i64), i64, dp, dp]
@@ -53,7 +56,7 @@ def lib():
     L.vkto_flip.argtypes = [vp, ctypes.c_int, i64, i64, i64, ctypes.c_int, vp]
     L.vkto_brick.argtypes = [vp, ctypes.c_int, i64, i64, i64, i64, i64, i64, i64, i64, i64,
                              ctypes.c_int, vp]
-    for f in ("vkto_correlate", "vkto_correlate_points",
+    for f in ("vkto_correlate", "vkto_correlate_box", "vkto_correlate_points",
               "vkto_store_float_filter", "vkto_store_int_filter",
               "vkto_fill_raw", "vkto_fill_range", "vkto_resample_linear", "vkto_flip",
               "vkto_brick"):
@@ -106,6 +109,24 @@ def correlate(src, w, mode="clamp", z_range=None, nthreads=0, with_abs=True):
                               _dp(w), _mode(mode), z0, z1, _dp(T),
                               _dp(A) if with_abs else None, int(nthreads))
     _check(rc, "correlate")
+    return (T, A) if with_abs else T
+
+
+def correlate_box(src, w, mode, first, last, nthreads=0, with_abs=True):
+    """T (and A_abs) on the half-open box [first, last), first/last = (x, y,
+    z), read through the address mode at the volume's faces; shape (nz, ny,
+    nx)."""
+    src = _volume(src)
+    w, k = _filter(w)
+    Z, Y, X = src.shape
+    (x0, y0, z0), (x1, y1, z1) = first, last
+    T = np.empty((max(z1 - z0, 0), max(y1 - y0, 0), max(x1 - x0, 0)), np.float64)
+    A = np.empty_like(T) if with_abs else None
+    rc = lib().vkto_correlate_box(src.ctypes.data, _FMT[src.dtype], X, Y, Z, k,
+                                  _dp(w), _mode(mode), int(x0), int(y0), int(z0),
+                                  int(x1), int(y1), int(z1), _dp(T),
+                                  _dp(A) if with_abs else None, int(nthreads))
+    _check(rc, "correlate_box")
     return (T, A) if with_abs else T
 
 

@@ -111,41 +111,48 @@ static int check_filter_args(const void* src, int fmt, int64_t X, int64_t Y,
 
 typedef struct {
     const void* src; int fmt; int64_t X, Y, Z; int k; const double* w; int mode;
-    int64_t z0, z1; double* T; double* A;
+    int64_t x0, y0, z0, x1, y1, z1; /* the output box, half-open */
+    double* T; double* A;
     int64_t zbeg, zend; /* this worker's planes */
 } job_t;
 
 static void* worker(void* p)
 {
     job_t* j = (job_t*)p;
-    const int64_t XY = j->X * j->Y;
+    const int64_t nx = j->x1 - j->x0, ny = j->y1 - j->y0;
     for (int64_t z = j->zbeg; z < j->zend; ++z)
-        for (int64_t y = 0; y < j->Y; ++y)
-            for (int64_t x = 0; x < j->X; ++x) {
-                int64_t o = (z - j->z0) * XY + y * j->X + x;
+        for (int64_t y = j->y0; y < j->y1; ++y)
+            for (int64_t x = j->x0; x < j->x1; ++x) {
+                int64_t o = ((z - j->z0) * ny + (y - j->y0)) * nx + (x - j->x0);
                 one_cell(j->src, j->fmt, j->X, j->Y, j->Z, j->k, j->w, j->mode,
                          x, y, z, &j->T[o], j->A ? &j->A[o] : NULL);
             }
     return NULL;
 }
 
-int vkto_correlate(const void* src, int fmt, int64_t X, int64_t Y, int64_t Z,
-                   int k, const double* w, int mode, int64_t z0, int64_t z1,
-                   double* T, double* Aabs, int nthreads)
+/* Every cell of the half-open box, the z range split over nthreads threads
+ * (each cell is independent, so the split changes no result). */
+static int correlate_box(const void* src, int fmt, int64_t X, int64_t Y,
+                         int64_t Z, int k, const double* w, int mode,
+                         int64_t x0, int64_t y0, int64_t z0, int64_t x1,
+                         int64_t y1, int64_t z1, double* T, double* Aabs,
+                         int nthreads)
 {
     if (check_filter_args(src, fmt, X, Y, Z, k, w, mode)) return -1;
-    if (!T || z0 < 0 || z1 > Z || z0 > z1) return -1;
+    if (!T || x0 < 0 || y0 < 0 || z0 < 0 || x1 > X || y1 > Y || z1 > Z ||
+        x0 > x1 || y0 > y1 || z0 > z1)
+        return -1;
     if (nthreads <= 0) nthreads = (int)sysconf(_SC_NPROCESSORS_ONLN);
     if (nthreads < 1) nthreads = 1;
     int64_t nz = z1 - z0;
-    if (nz == 0) return 0;
+    if (nz == 0 || x0 == x1 || y0 == y1) return 0;
     if (nthreads > nz) nthreads = (int)nz;
 
     job_t* jobs = (job_t*)calloc((size_t)nthreads, sizeof(job_t));
     pthread_t* th = (pthread_t*)calloc((size_t)nthreads, sizeof(pthread_t));
     if (!jobs || !th) { free(jobs); free(th); return -2; }
     for (int t = 0; t < nthreads; ++t) {
-        job_t j = {src, fmt, X, Y, Z, k, w, mode, z0, z1, T, Aabs,
+        job_t j = {src, fmt, X, Y, Z, k, w, mode, x0, y0, z0, x1, y1, z1, T, Aabs,
                    z0 + nz * t / nthreads, z0 + nz * (t + 1) / nthreads};
         jobs[t] = j;
     }
@@ -160,6 +167,23 @@ int vkto_correlate(const void* src, int fmt, int64_t X, int64_t Y, int64_t Z,
     free(jobs);
     free(th);
     return 0;
+}
+
+int vkto_correlate(const void* src, int fmt, int64_t X, int64_t Y, int64_t Z,
+                   int k, const double* w, int mode, int64_t z0, int64_t z1,
+                   double* T, double* Aabs, int nthreads)
+{
+    return correlate_box(src, fmt, X, Y, Z, k, w, mode, 0, 0, z0, X, Y, z1, T,
+                         Aabs, nthreads);
+}
+
+int vkto_correlate_box(const void* src, int fmt, int64_t X, int64_t Y,
+                       int64_t Z, int k, const double* w, int mode, int64_t x0,
+                       int64_t y0, int64_t z0, int64_t x1, int64_t y1,
+                       int64_t z1, double* T, double* Aabs, int nthreads)
+{
+    return correlate_box(src, fmt, X, Y, Z, k, w, mode, x0, y0, z0, x1, y1, z1,
+                         T, Aabs, nthreads);
 }
 
 int vkto_correlate_points(const void* src, int fmt, int64_t X, int64_t Y,

@@ -53,6 +53,14 @@ int vkto_correlate(const void* src, int fmt, int64_t X, int64_t Y, int64_t Z,
                    int k, const double* w, int mode, int64_t z0, int64_t z1,
                    double* T, double* Aabs, int nthreads);
 
+/* The same sum on the half-open box [x0,x1) x [y0,y1) x [z0,z1) of the
+ * volume (the address mode still acts at the volume's faces, not the box's).
+ * T and Aabs (may be NULL) hold the box, x fastest. */
+int vkto_correlate_box(const void* src, int fmt, int64_t X, int64_t Y,
+                       int64_t Z, int k, const double* w, int mode, int64_t x0,
+                       int64_t y0, int64_t z0, int64_t x1, int64_t y1,
+                       int64_t z1, double* T, double* Aabs, int nthreads);
+
 /* The same sum at npts explicit cells; pts holds (x, y, z) triples. */
 int vkto_correlate_points(const void* src, int fmt, int64_t X, int64_t Y,
                           int64_t Z, int k, const double* w, int mode,

@@ -320,6 +320,26 @@ def test_points_agree_with_full_volume(orc):
         assert np.array_equal(Ap, A[pts[:, 2], pts[:, 1], pts[:, 0]])
 
 
+def test_box_agrees_with_full_volume(orc):
+    """The box form equals the (pinned) whole-volume sum on its cells, for
+    boxes touching every face, interior boxes, empty boxes and any thread
+    count; the address mode acts at the volume's faces, not the box's."""
+    g = np.random.default_rng(16)
+    src = g.integers(0, 256, (11, 9, 13)).astype(np.uint8)
+    w = g.standard_normal((5, 5, 5))
+    for m in MODES:
+        T, A = orc.correlate(src, w, m)
+        for first, last in (((0, 0, 0), (13, 9, 11)), ((0, 0, 0), (3, 2, 4)),
+                            ((10, 7, 8), (13, 9, 11)), ((4, 3, 2), (9, 6, 7)),
+                            ((5, 5, 5), (5, 9, 11))):
+            for nt in (1, 3):
+                Tb, Ab = orc.correlate_box(src, w, m, first, last, nthreads=nt)
+                sl = tuple(slice(a, b) for a, b in zip(first[::-1], last[::-1]))
+                assert np.array_equal(Tb, T[sl]) and np.array_equal(Ab, A[sl]), (m, first)
+    with pytest.raises(ValueError):
+        orc.correlate_box(src, w, "clamp", (0, 0, 0), (14, 9, 11))
+
+
 def test_z_range_and_threads(orc):
     g = np.random.default_rng(15)
     src = g.random((10, 6, 7)).astype(np.float32)
