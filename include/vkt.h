@@ -113,7 +113,9 @@ vktError vktStructuredVolumeGetDims(vktStructuredVolume volume, int32_t* dimX,
 vktError vktStructuredVolumeGetDataFormat(vktStructuredVolume volume,
                                           vktDataFormat* format);
 
-/* ---- filters ------------------------------------------------------------ */
+/* ---- filters (paper Sec. 3.2 "Volume Manipulation": ApplyFilter applies
+ *      user-specified convolution kernels such as edge detection or a
+ *      Gaussian blur; Sec. 4.3 benchmarks the Gaussian blur) --------------- */
 
 /* A dense k*k*k filter of float weights, copied at creation (host array of
  * k^3 floats, a fastest: w[a + k*(b + k*c)] multiplies the cell at offset
@@ -122,14 +124,20 @@ vktError vktStructuredVolumeGetDataFormat(vktStructuredVolume volume,
  * vktOutOfMemory. */
 vktError vktFilterCreate(vktFilter* filter, int32_t k, const float* weights);
 
-/* A dense k*k*k filter of integer weights with a divisor: the result is
- * sum(w*s) / divisor, rounded half-up and saturated for integer formats
- * (computed exactly).  |w| < 2^23, divisor in [1, 2^29].
+/* A dense k*k*k filter of integer weights with a divisor (the paper's
+ * user-specified kernels written as integers, e.g. a box filter with divisor
+ * k^3, Sec. 3.2): the result is sum(w*s) / divisor, rounded half-up and
+ * saturated for integer formats (computed exactly).  |w| < 2^23, divisor in [1, 2^29].
  * Errors: vktInvalidValue for NULL pointers, k not odd in [1, 15], a weight
  * out of range or a divisor out of range; vktOutOfMemory. */
 vktError vktFilterCreateInt(vktFilter* filter, int32_t k, const int32_t* weights,
                             int32_t divisor);
 
+/* Release a filter created by vktFilterCreate / vktFilterCreateInt and its
+ * device copies of the weights (create / destroy pairs of handles as in the
+ * paper's C99 example, Fig. 4).  Work already enqueued with the filter must
+ * have completed (the device buffers are freed with hipFree).
+ * Errors: vktInvalidValue for a handle that is not a live filter. */
 vktError vktFilterDestroy(vktFilter filter);
 
 /* ---- Fill / FillRange (paper Sec. 3.2 "Volume Manipulation", Fig. 4) ---- */
@@ -184,7 +192,9 @@ vktError vktApplyFilterRange(vktStructuredVolume dst, vktStructuredVolume src,
                              int32_t firstZ, int32_t lastX, int32_t lastY,
                              int32_t lastZ, vktAddressMode mode);
 
-/* Batched form: dst[i] = ApplyFilter(src[i], filters[i]) for i < n, each
+/* Batched form (paper Sec. 4.3 filters every structured dataset of its
+ * benchmark set; Sec. 3.2 domain decomposition yields many bricks to filter):
+ * dst[i] = ApplyFilter(src[i], filters[i]) for i < n, each
  * pair exactly as vktApplyFilter would compute it, for volumes of different
  * sizes and filters of different k.  The pairs are grouped into arithmetic
  * classes (format, k, path); each class runs as one persistent launch whose
@@ -313,7 +323,33 @@ vktError vktGetInt8Matrix(int* enable);
 /* *separable = 1 if the filter's weights are rank 1 (as above), else 0. */
 vktError vktFilterIsSeparable(vktFilter filter, int* separable);
 
-/* Wait for the calling thread's stream; reports faults of enqueued work. */
+/* Arithmetic path of an ApplyFilter call. */
+typedef enum vktFilterPath {
+    vktFilterPathVectorFP32 = 0,   /* FP32 multiply-adds on the vector ALUs (exact
+                                      int32 sums for integer filters whose FP32
+                                      sums could pass 2^24) */
+    vktFilterPathDot8 = 1,         /* 8-bit dot products (uint8 cells, small
+                                      integer weights), exact int32 sums */
+    vktFilterPathInt8Matrix = 2,   /* int8 x int8 matrix-core products, exact */
+    vktFilterPathSplitMatrix = 3,  /* 16-bit operand pieces on the matrix cores,
+                                      FP32 accumulation */
+    vktFilterPathSeparable = 4     /* rank-1 form: three 1-D passes in FP32 */
+} vktFilterPath;
+
+/* The path vktApplyFilter(dst, src, filter, mode) would take on the calling
+ * thread now (its precision, separable and int8-matrix settings, and the
+ * volumes' sizes and alignment), chosen by the same planning code as the
+ * call itself; nothing is enqueued.  *products receives the number of
+ * partial products per multiply-add on the split matrix path (uint8 cells 2,
+ * uint16 4, Float32 3 or 6) and 1 on every other path.  products may be NULL.
+ * Ownership: nothing is retained.  Errors: as vktApplyFilter, plus
+ * vktInvalidValue for a NULL path. */
+vktError vktGetFilterPath(vktStructuredVolume dst, vktStructuredVolume src,
+                          vktFilter filter, vktAddressMode mode,
+                          vktFilterPath* path, int32_t* products);
+
+/* Wait for the calling thread's stream (the stream of its execution state,
+ * paper Sec. 3.1); reports faults of enqueued work as vktDeviceError. */
 vktError vktSynchronize(void);
 
 const char* vktGetErrorString(vktError error);

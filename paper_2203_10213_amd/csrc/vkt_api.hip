@@ -807,6 +807,26 @@ vktError vktFilterIsSeparable(vktFilter filter, int* separable)
     return vktNoError;
 }
 
+vktError vktGetFilterPath(vktStructuredVolume dst, vktStructuredVolume src, vktFilter filt,
+                          vktAddressMode mode, vktFilterPath* path, int32_t* products)
+{
+    if (!path) return vktInvalidValue;
+    vkt::FilterJob j;
+    bool mfma = false, six = false;
+    const vktError e = vkt::build_job(dst, src, filt, mode, state().precision, j, mfma, six);
+    if (e != vktNoError) return e;
+    int32_t p = 1;
+    if (j.sep) *path = vktFilterPathSeparable;
+    else if (mfma) {
+        *path = vktFilterPathSplitMatrix;
+        p = j.fmt == vktDataFormatUInt8 ? 2 : (j.fmt == vktDataFormatUInt16 ? 4 : (six ? 6 : 3));
+    } else if (j.i8mma) *path = vktFilterPathInt8Matrix;
+    else if (j.dot4) *path = vktFilterPathDot8;
+    else *path = vktFilterPathVectorFP32;
+    if (products) *products = p;
+    return vktNoError;
+}
+
 vktError vktSetAutotune(int enable)
 {
     state().autotune = enable != 0;

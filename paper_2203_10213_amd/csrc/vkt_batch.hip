@@ -145,8 +145,13 @@ struct Plan {
     }
 };
 
+// Plan cache, least recently used first.  Plans are shared: a caller holds
+// its plan until its graph launch has been enqueued, so a plan evicted by
+// another thread meanwhile stays alive until then (the graph itself may still
+// be running when the last holder lets go; hipFree of the plan's buffer waits
+// for it).
 std::mutex g_plan_mu;
-std::vector<std::unique_ptr<Plan>> g_plans;  // most recent last
+std::vector<std::shared_ptr<Plan>> g_plans;
 constexpr size_t kMaxPlans = 16;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -187,6 +192,23 @@ struct Triple {
     ClassKey key;
     const vktFilter_* f;
 };
+
+// Tuning-table key of one class of a batch, and the depth the table holds
+// for it (0: none).
+TuneKey tune_key(const std::vector<Triple>& tr, const ClassPlan& cp)
+{
+    std::vector<FilterJob> jobs;
+    for (int idx : cp.members) jobs.push_back(tr[idx].j);
+    return TuneKey{cp.key, size_class_of(jobs)};
+}
+
+int tuned_tz(const TuneKey& tk)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    auto it = g_tune.find(tk);
+    return it != g_tune.end() ? it->second : 0;
+}
 
 // Build (or rebuild for another slab depth) the host-side arrays of one class.
 void class_arrays(const std::vector<Triple>& tr, ClassPlan& cp, std::vector<VolDesc>& descs,
@@ -286,9 +308,9 @@ float time_class(const std::vector<Triple>& tr, ClassPlan& cp, char* base, int t
 }
 
 vktError build_plan(const std::vector<Triple>& tr, std::vector<uintptr_t>&& sig, bool tune,
-                    hipStream_t stream, Plan*& out)
+                    hipStream_t stream, std::shared_ptr<Plan>& out)
 {
-    auto plan = std::make_unique<Plan>();
+    auto plan = std::make_shared<Plan>();
     plan->sig = std::move(sig);
     if (hipGetDevice(&plan->device) != hipSuccess) return vktDeviceError;
     int cus = 0;
@@ -341,19 +363,10 @@ vktError build_plan(const std::vector<Triple>& tr, std::vector<uintptr_t>&& sig,
     e = hipMemset(plan->dbuf, 0, bytes);  // queue counters start at zero
     if (e != hipSuccess) return from_hip(e);
 
-    std::vector<FilterJob> jobs;
     for (auto& cp : plan->classes) {
         const ClassGeom geom = class_geom(cp.key);
-        jobs.clear();
-        for (int idx : cp.members) jobs.push_back(tr[idx].j);
-        const TuneKey tk{cp.key, size_class_of(jobs)};
-        int tz = 0;
-        {
-            std::lock_guard<std::mutex> lk(g_tune_mu);
-            tune_load_locked();
-            auto it = g_tune.find(tk);
-            if (it != g_tune.end()) tz = it->second;
-        }
+        const TuneKey tk = tune_key(tr, cp);
+        int tz = tuned_tz(tk);
         if (tz == 0 && tune) {
             // autotune: time candidate slab depths on the real batch
             float best = -1.f;
@@ -401,29 +414,28 @@ vktError build_plan(const std::vector<Triple>& tr, std::vector<uintptr_t>&& sig,
     if (e == hipSuccess) e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) return from_hip(e);
 
-    std::lock_guard<std::mutex> lk(g_plan_mu);
-    if (g_plans.size() >= kMaxPlans) g_plans.erase(g_plans.begin());  // hipFree waits
-    g_plans.push_back(std::move(plan));
-    out = g_plans.back().get();
+    out = plan;
+    std::shared_ptr<Plan> evicted;  // released after the lock (hipFree waits)
+    {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        if (g_plans.size() >= kMaxPlans) {
+            evicted = std::move(g_plans.front());
+            g_plans.erase(g_plans.begin());
+        }
+        g_plans.push_back(std::move(plan));
+    }
     return vktNoError;
 }
 
-}  // namespace
-}  // namespace vkt
-
-extern "C" {
-
-vktError vktApplyFilterBatched(int32_t n, const vktStructuredVolume* dst,
-                               const vktStructuredVolume* src, const vktFilter* filters,
-                               vktAddressMode mode)
+// Validate and plan every triple of a batch exactly as vktApplyFilter would,
+// check that no output overlaps any volume of the batch, and collect the
+// batch signature (the plan cache key).
+vktError prepare_batch(int32_t n, const vktStructuredVolume* dst, const vktStructuredVolume* src,
+                       const vktFilter* filters, vktAddressMode mode, vktPrecision prec,
+                       hipStream_t stream, std::vector<Triple>& tr, std::vector<uintptr_t>& sig)
 {
-    using namespace vkt;
-    if (n < 0 || (n > 0 && (!dst || !src || !filters))) return vktInvalidValue;
-    if (n == 0) return vktNoError;
-    const vktPrecision prec = thread_precision();
-    hipStream_t stream = thread_stream();
-    std::vector<Triple> tr(n);
-    std::vector<uintptr_t> sig;
+    tr.assign(n, Triple{});
+    sig.clear();
     sig.reserve(4 + 6 * (size_t)n);
     sig.push_back((uintptr_t)n);
     sig.push_back((uintptr_t)mode);
@@ -454,22 +466,54 @@ vktError vktApplyFilterBatched(int32_t n, const vktStructuredVolume* dst,
         dr.push_back({(uintptr_t)tr[i].j.dst, (uintptr_t)tr[i].j.dst + b});
         sr.push_back({(uintptr_t)tr[i].j.src, (uintptr_t)tr[i].j.src + b});
     }
-    std::vector<std::pair<uintptr_t, uintptr_t>> all = sr;
     std::sort(dr.begin(), dr.end());
     for (size_t i = 1; i < dr.size(); ++i)
         if (dr[i].first < dr[i - 1].second) return vktInvalidValue;
-    for (const auto& d : dr)
-        for (const auto& s : all)
-            if (d.first < s.second && s.first < d.second) return vktInvalidValue;
+    // sources sorted by start with the running maximum of their ends: an
+    // output [a, b) meets a source iff some source starting before b ends
+    // after a
+    std::sort(sr.begin(), sr.end());
+    std::vector<uintptr_t> max_end(sr.size());
+    for (size_t i = 0; i < sr.size(); ++i)
+        max_end[i] = std::max(sr[i].second, i ? max_end[i - 1] : (uintptr_t)0);
+    for (const auto& d : dr) {
+        const size_t m = (size_t)(std::lower_bound(sr.begin(), sr.end(),
+                                                   std::make_pair(d.second, (uintptr_t)0)) -
+                                  sr.begin());
+        if (m > 0 && max_end[m - 1] > d.first) return vktInvalidValue;
+    }
+    return vktNoError;
+}
 
-    Plan* plan = nullptr;
+}  // namespace
+}  // namespace vkt
+
+extern "C" {
+
+vktError vktApplyFilterBatched(int32_t n, const vktStructuredVolume* dst,
+                               const vktStructuredVolume* src, const vktFilter* filters,
+                               vktAddressMode mode)
+{
+    using namespace vkt;
+    if (n < 0 || (n > 0 && (!dst || !src || !filters))) return vktInvalidValue;
+    if (n == 0) return vktNoError;
+    const vktPrecision prec = thread_precision();
+    hipStream_t stream = thread_stream();
+    std::vector<Triple> tr;
+    std::vector<uintptr_t> sig;
+    const vktError ve = prepare_batch(n, dst, src, filters, mode, prec, stream, tr, sig);
+    if (ve != vktNoError) return ve;
+
+    std::shared_ptr<Plan> plan;
     {
-        std::lock_guard<std::mutex> lk(g_plan_mu);
         int dev = 0;
         (void)hipGetDevice(&dev);
+        std::lock_guard<std::mutex> lk(g_plan_mu);
         for (auto it = g_plans.begin(); it != g_plans.end(); ++it)
             if ((*it)->sig == sig && (*it)->device == dev) {
-                plan = it->get();
+                plan = *it;
+                g_plans.erase(it);        // a hit becomes the most recently used
+                g_plans.push_back(plan);
                 break;
             }
     }

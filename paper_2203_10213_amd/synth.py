@@ -13,8 +13,9 @@ oracle consume what it returns.  Volumes are returned with shape (Z, Y, X)
 """
 import numpy as np
 
-SEEDS = {"c1": 1001, "c2a": 2001, "c2b": 2002, "c3": 3001, "c3a_w": 3007,
-         "c3b_w": 3009, "c4": 4001, "c5": 5001, "c5_blocks": 5002}
+SEEDS = {"c1": 1001, "c2a": 2001, "c2b": 2002, "c2_blocks": 2003, "c3": 3001,
+         "c3_blocks": 3002, "c3a_w": 3007, "c3b_w": 3009, "c4": 4001, "c5": 5001,
+         "c5_blocks": 5002}
 
 
 def rng(seed):
@@ -42,6 +43,20 @@ def random_l1(k, seed):
     """Dense N(0,1) weights normalised to unit L1 norm in FP64, then float32."""
     w = rng(seed).standard_normal((k, k, k))
     return (w / np.abs(w).sum()).astype(np.float32)
+
+
+def sample_blocks(shape, n_random, seed, size=32):
+    """Origins (x, y, z) of size^3 blocks of a (Z, Y, X) volume at which
+    results are checked: the 8 corner blocks, then n_random blocks with
+    origins uniform over the volume (seeded)."""
+    Z, Y, X = shape
+    bx, by, bz = min(size, X), min(size, Y), min(size, Z)
+    out = [(x, y, z) for z in (0, Z - bz) for y in (0, Y - by) for x in (0, X - bx)]
+    g = rng(seed)
+    for _ in range(n_random):
+        out.append((int(g.integers(0, X - bx + 1)), int(g.integers(0, Y - by + 1)),
+                    int(g.integers(0, Z - bz + 1))))
+    return out
 
 
 # ---------------------------------------------------------------- volumes --

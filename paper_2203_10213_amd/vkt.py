@@ -21,6 +21,11 @@ vktDataFormatUInt8, vktDataFormatUInt16, vktDataFormatFloat32 = range(3)
 vktAddressModeClamp, vktAddressModeWrap, vktAddressModeMirror, vktAddressModeBorder = range(4)
 vktPrecisionAuto, vktPrecisionFP32, vktPrecisionSplitBF16, vktPrecisionSplitBF16x6 = range(4)
 vktAxisX, vktAxisY, vktAxisZ = range(3)
+(vktFilterPathVectorFP32, vktFilterPathDot8, vktFilterPathInt8Matrix,
+ vktFilterPathSplitMatrix, vktFilterPathSeparable) = range(5)
+FILTER_PATHS = {vktFilterPathVectorFP32: "valu", vktFilterPathDot8: "dot4",
+                vktFilterPathInt8Matrix: "i8mma", vktFilterPathSplitMatrix: "mfma",
+                vktFilterPathSeparable: "sep"}
 
 MODES = {"clamp": vktAddressModeClamp, "wrap": vktAddressModeWrap,
          "mirror": vktAddressModeMirror, "border": vktAddressModeBorder}
@@ -65,6 +70,7 @@ SIGNATURES = {
     "vktSetInt8Matrix": [ctypes.c_int],
     "vktGetInt8Matrix": [ctypes.POINTER(ctypes.c_int)],
     "vktFilterIsSeparable": [_P, ctypes.POINTER(ctypes.c_int)],
+    "vktGetFilterPath": [_P, _P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _PI],
     "vktSetStream": [_P],
     "vktGetStream": [_PP],
     "vktSetPrecision": [ctypes.c_int],
@@ -325,6 +331,17 @@ def vktFilterIsSeparable(filt):
     v = ctypes.c_int()
     _ok(lib().vktFilterIsSeparable(filt, ctypes.byref(v)), "vktFilterIsSeparable")
     return bool(v.value)
+
+
+def vktGetFilterPath(dst, src, filt, mode=vktAddressModeClamp):
+    """(path, products) that vktApplyFilter(dst, src, filt, mode) would take
+    on this thread now; path is a vktFilterPath value."""
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    p = ctypes.c_int()
+    n = ctypes.c_int32()
+    _ok(lib().vktGetFilterPath(dst, src, filt, m, ctypes.byref(p), ctypes.byref(n)),
+        "vktGetFilterPath")
+    return p.value, n.value
 
 
 def vktSynchronize():

@@ -98,3 +98,35 @@ def sample_points(shape, n, seed, edges=True):
         pts.append(np.array([[min(max(a, 0), X - 1), min(max(b, 0), Y - 1),
                               min(max(c, 0), Z - 1)] for a, b, c in cs]))
     return np.concatenate(pts).astype(np.int64)
+
+
+def device_blocks(t, origins, size=32):
+    """The size^3 blocks of device tensor t (Z, Y, X) at origins (x, y, z),
+    stacked and copied to the host."""
+    import torch
+    Z, Y, X = t.shape
+    bx, by, bz = min(size, X), min(size, Y), min(size, Z)
+    return torch.stack([t[z:z + bz, y:y + by, x:x + bx] for x, y, z in origins]).cpu().numpy()
+
+
+def oracle_blocks(orc, src, w, mode, origins, size=32):
+    """T and A_abs (FP64) on the blocks at origins, read through the whole
+    volume and the address mode."""
+    Z, Y, X = src.shape
+    bx, by, bz = min(size, X), min(size, Y), min(size, Z)
+    Ts, As = [], []
+    for x, y, z in origins:
+        T, A = orc.correlate_box(src, np.asarray(w, np.float64), mode, (x, y, z),
+                                 (x + bx, y + by, z + bz), nthreads=ORACLE_THREADS)
+        Ts.append(T)
+        As.append(A)
+    return np.stack(Ts), np.stack(As)
+
+
+def float_error_stats(got, T, A):
+    """Max and RMS of |gpu - T| and of e = |gpu - T| / sum|w||s| over the
+    cells (float32 results)."""
+    d = np.abs(got.astype(np.float64) - T)
+    e = np.where(A > 0, d / np.maximum(A, 1e-300), np.where(d == 0, 0.0, np.inf))
+    return dict(max_abs=float(d.max()), rms_abs=float(np.sqrt(np.mean(d * d))),
+                max_rel=float(e.max()), rms_rel=float(np.sqrt(np.mean(e * e))))

@@ -5,7 +5,7 @@ batches replay a cached hipGraph and must track new input data."""
 import numpy as np
 import pytest
 
-from _gpu import check_against_oracle, sentinel_like, to_device
+from _gpu import check_against_oracle, sample_points, sentinel_like, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -166,7 +166,8 @@ def test_batched_errors():
 def test_c4_256_uint16_volumes_mixed_k(orc):
     """256 uint16 gamma(2, 2000) volumes, axes U{32..256}, k in {3,5,7},
     Gaussian sigma k/4, clamp: batched == 256 single launches bit for bit;
-    8 volumes against the oracle on every cell."""
+    every volume against the oracle on 10000 random cells plus its corner
+    and edge cells (within 1 LSB), 8 of them on every cell."""
     import torch
     from paper_2203_10213_amd import synth, vkt
     vols, ks = synth.gamma_u16_volumes(256, synth.SEEDS["c4"])
@@ -186,12 +187,70 @@ def test_c4_256_uint16_volumes_mixed_k(orc):
         for i in range(256):
             assert torch.equal(dsts[i].view(torch.int16), singles[i].view(torch.int16)), i
         g = np.random.default_rng(404)
-        for i in g.choice(256, 8, replace=False):
+        full = set(int(i) for i in g.choice(256, 8, replace=False))
+        for i in range(256):
             out = dsts[i].view(torch.int16).cpu().numpy().view(np.uint16)
+            pts = None if i in full else sample_points(vols[i].shape, 10000, 4040 + i)
             check_against_oracle(orc, vols[i], synth.gaussian_weights(ks[i], ks[i] / 4),
-                                 "clamp", out, what=f"C4 volume {i}")
+                                 "clamp", out, pts=pts, what=f"C4 volume {i}")
     finally:
         for h in hs + hd + h1:
             vkt.vktStructuredVolumeDestroy(h)
         for f in filts.values():
             vkt.vktFilterDestroy(f)
+
+
+def test_two_threads_fill_plan_cache_past_capacity():
+    """Two threads, each on its own stream with its own outputs, run batched
+    calls over 10 batches apiece (20 signatures: more than the 16 cached
+    plans), three rounds, so each thread's plans are evicted while the other
+    may be launching them.  Every output equals the single-volume result."""
+    import threading
+
+    import torch
+    from paper_2203_10213_amd import vkt
+    per_thread = []
+    for t in range(2):
+        bs = []
+        for i in range(10):
+            spec = MIXED[(i + 3 * t) % len(MIXED)]
+            spec2 = MIXED[(i + 5 * t + 1) % len(MIXED)]
+            bs.append(Batch([spec, spec2], 500 + 37 * t + i))
+        per_thread.append(bs)
+    want = [[[b.single(j) for j in range(len(b.items))] for b in bs] for bs in per_thread]
+    errors = []
+
+    def worker(t):
+        try:
+            s = torch.cuda.Stream()
+            vkt.vktSetStream(s)
+            vkt.vktSetPrecision("auto")
+            vkt.vktSetAutotune(False)
+            for _ in range(3):
+                for b in per_thread[t]:
+                    it = b.items
+                    vkt.vktApplyFilterBatched([x["hd"] for x in it], [x["hs"] for x in it],
+                                              [x["hf"] for x in it], "clamp")
+            vkt.vktSynchronize()
+        except Exception as e:  # reported by the main thread
+            errors.append((t, repr(e)))
+
+    try:
+        ths = [threading.Thread(target=worker, args=(t,)) for t in range(2)]
+        for th in ths:
+            th.start()
+        for th in ths:
+            th.join(timeout=100)
+        assert not any(th.is_alive() for th in ths), "batched calls did not return"
+        assert not errors, errors
+        torch.cuda.synchronize()
+        for t, bs in enumerate(per_thread):
+            for i, b in enumerate(bs):
+                for j, x in enumerate(b.items):
+                    got = x["d_t"].cpu().numpy()
+                    assert np.array_equal(got.view(np.uint8), want[t][i][j].view(np.uint8)), \
+                        (t, i, j)
+    finally:
+        for bs in per_thread:
+            for b in bs:
+                b.close()
