@@ -137,8 +137,16 @@ struct Plan {
     std::vector<ClassPlan> classes;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // recorded after every launch of the graph: an evicted plan is destroyed
+    // only once its last launch has finished (the launch may still be queued
+    // on another thread's stream when the plan leaves the cache)
+    hipEvent_t done = nullptr;
     ~Plan()
     {
+        if (done) {
+            (void)hipEventSynchronize(done);
+            (void)hipEventDestroy(done);
+        }
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (dbuf) (void)hipFree(dbuf);
@@ -412,6 +420,7 @@ vktError build_plan(const std::vector<Triple>& tr, std::vector<uintptr_t>&& sig,
         e = hipGraphAddKernelNode(&node, plan->graph, nullptr, 0, &p);
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&plan->done, hipEventDisableTiming);
     if (e != hipSuccess) return from_hip(e);
 
     out = plan;
@@ -521,7 +530,9 @@ vktError vktApplyFilterBatched(int32_t n, const vktStructuredVolume* dst,
         const vktError e = build_plan(tr, std::move(sig), thread_autotune(), stream, plan);
         if (e != vktNoError) return e;
     }
-    return from_hip(hipGraphLaunch(plan->exec, stream));
+    hipError_t e = hipGraphLaunch(plan->exec, stream);
+    if (e == hipSuccess) e = hipEventRecord(plan->done, stream);
+    return from_hip(e);
 }
 
 }  // extern "C"
