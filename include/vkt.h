@@ -215,6 +215,32 @@ vktError vktApplyFilterBatched(int32_t n, const vktStructuredVolume* dst,
                                const vktStructuredVolume* src,
                                const vktFilter* filters, vktAddressMode mode);
 
+/* Allocation-free batched form, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, validation and results as
+ * vktApplyFilterBatched -- the same class kernels, slab depths (the tuning
+ * table's entry, else the default; this call never tunes) and summation
+ * order -- but no plan, graph or device buffer is created: the batch's
+ * descriptors, work lists, work-queue counters and weight pools go to a
+ * static device array of the library, 8 MiB per GPU, held by each GPU the
+ * library runs on until the process ends.  Each call uploads that data
+ * (counters cleared) with copies on the calling thread's stream and then
+ * launches the class kernels one after another on the same stream; it calls
+ * no hipMalloc / hipFree and no allocating library routine.  Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU (from other
+ * threads or on other streams) race and must be serialised by the caller;
+ * calls in order on one stream are safe.  The host waits only for the
+ * previous call's upload to have been read.
+ * Limit: the batch's descriptors (one per volume), work items (one per output
+ * tile-slab of every volume) and weight pools must fit the 8 MiB array;
+ * otherwise vktUnsupported is returned before anything is enqueued.
+ * Errors: as vktApplyFilterBatched, plus vktUnsupported for a batch beyond
+ * the limit. */
+vktError vktApplyFilterBatchedNoAlloc(int32_t n, const vktStructuredVolume* dst,
+                                      const vktStructuredVolume* src,
+                                      const vktFilter* filters,
+                                      vktAddressMode mode);
+
 /* ---- Resample and Flip (paper Sec. 3.2 core and transform algorithms;
  *      Sec. 4 downscales by two and flips along the longest axis) --------- */
 

@@ -494,6 +494,154 @@ vktError prepare_batch(int32_t n, const vktStructuredVolume* dst, const vktStruc
     return vktNoError;
 }
 
+// ---- allocation-free form ---------------------------------------------------
+//
+// The batch's descriptors, work lists, work-queue counters and weight pools
+// go to this file-scope device array instead of a plan buffer.  Host code
+// never passes the array's name to a kernel or a copy (on the host it is a
+// stand-in, not a device address): it uses the address that
+// hipGetSymbolAddress returns for the current device, looked up once per
+// device.
+constexpr size_t kNoAllocBytes = size_t(8) << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+struct NoAllocDevice {
+    unsigned char* ptr = nullptr;       // this device's copy of `scratch`
+    std::vector<unsigned char> staging; // host image of the array's head
+    hipEvent_t copied = nullptr;        // the last upload from `staging` is done
+    bool pending = false;
+    std::mutex mu;                      // one call per device at a time (host side)
+};
+std::mutex g_noalloc_mu;
+std::map<int, std::unique_ptr<NoAllocDevice>> g_noalloc;
+
+// Set-up on the first call on a device, with that device current.
+vktError noalloc_device(int dev, NoAllocDevice*& out)
+{
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    auto it = g_noalloc.find(dev);
+    if (it == g_noalloc.end()) {
+        auto d = std::make_unique<NoAllocDevice>();
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return vktDeviceError;
+        e = hipEventCreateWithFlags(&d->copied, hipEventDisableTiming);
+        if (e != hipSuccess) return vktDeviceError;
+        d->ptr = static_cast<unsigned char*>(p);
+        d->staging.resize(kNoAllocBytes);
+        it = g_noalloc.emplace(dev, std::move(d)).first;
+    }
+    out = it->second.get();
+    return vktNoError;
+}
+
+vktError batched_no_alloc(const std::vector<Triple>& tr, hipStream_t stream)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return vktDeviceError;
+    NoAllocDevice* nd = nullptr;
+    vktError ve = noalloc_device(dev, nd);
+    if (ve != vktNoError) return ve;
+
+    // plan every class as the cached form does (same slab depths: the tuning
+    // table's entry, else the default; this form never times candidates)
+    std::map<ClassKey, std::vector<int>> groups;
+    for (size_t i = 0; i < tr.size(); ++i) groups[tr[i].key].push_back((int)i);
+    std::vector<ClassPlan> classes;
+    std::vector<std::vector<VolDesc>> descs(groups.size());
+    std::vector<std::vector<WorkItem>> items(groups.size());
+    std::vector<size_t> npool(groups.size());
+    // layout: the heads of all classes (descriptors, work list, counters),
+    // then the weight pools
+    size_t bytes = 0, c = 0;
+    for (auto& g : groups) {
+        ClassPlan cp;
+        cp.key = g.first;
+        cp.members = g.second;
+        cp.func = class_kernel(cp.key);
+        if (!cp.func) return vktUnsupported;
+        const ClassGeom geom = class_geom(cp.key);
+        int tz = tuned_tz(tune_key(tr, cp));
+        if (tz == 0) tz = default_tz(cp.key, geom);
+        cp.tz = std::max(tz, geom.tz_min);
+        std::vector<float> wf;
+        std::vector<int32_t> wi;
+        class_arrays(tr, cp, descs[c], items[c], wf, wi);
+        const size_t n3 = (size_t)class_weights(cp.key);
+        for (const auto& d : descs[c]) npool[c] = std::max(npool[c], (size_t)d.woff / n3 + 1);
+        cp.off_desc = bytes = align_up(bytes, 256);
+        bytes += descs[c].size() * sizeof(VolDesc);
+        cp.off_items = bytes = align_up(bytes, 256);
+        bytes += items[c].size() * sizeof(WorkItem);
+        cp.off_cnt = bytes = align_up(bytes, 256);
+        bytes += 2 * sizeof(uint32_t);
+        cp.grid = (unsigned)resident_wgs(cp.func);
+        classes.push_back(cp);
+        ++c;
+    }
+    for (size_t i = 0; i < classes.size(); ++i) {
+        ClassPlan& cp = classes[i];
+        const size_t n3 = (size_t)class_weights(cp.key);
+        cp.off_wf = bytes = align_up(bytes, 256);
+        bytes += (npool[i] * n3 + kWeightPad) * sizeof(float);
+        cp.off_wi = bytes = align_up(bytes, 256);
+        bytes += (npool[i] * n3 + kWeightPad) * sizeof(int32_t);
+    }
+    if (bytes > kNoAllocBytes) return vktUnsupported;  // the batch does not fit
+
+    std::lock_guard<std::mutex> lk(nd->mu);
+    // the previous upload must have read the staging image before it changes
+    if (nd->pending && hipEventSynchronize(nd->copied) != hipSuccess) return vktDeviceError;
+    nd->pending = false;
+    // image of the used region: descriptors, work lists, zeroed counters and
+    // zeroed weight pools (the upload clears the counters and the pools' pads;
+    // the weights come from the filters' device buffers below)
+    std::memset(nd->staging.data(), 0, bytes);
+    for (size_t i = 0; i < classes.size(); ++i) {
+        const ClassPlan& cp = classes[i];
+        std::memcpy(&nd->staging[cp.off_desc], descs[i].data(), descs[i].size() * sizeof(VolDesc));
+        std::memcpy(&nd->staging[cp.off_items], items[i].data(),
+                    items[i].size() * sizeof(WorkItem));
+    }
+    hipError_t e =
+        hipMemcpyAsync(nd->ptr, nd->staging.data(), bytes, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipEventRecord(nd->copied, stream);
+    if (e != hipSuccess) return from_hip(e);
+    nd->pending = true;
+    for (size_t i = 0; i < classes.size() && e == hipSuccess; ++i) {
+        ClassPlan& cp = classes[i];
+        const size_t n3 = (size_t)class_weights(cp.key);
+        std::map<uint32_t, const vktFilter_*> pool;
+        for (size_t m = 0; m < cp.members.size(); ++m)
+            pool.emplace(descs[i][m].woff, tr[cp.members[m]].f);
+        for (const auto& pf : pool) {
+            const vktFilter_* f = pf.second;
+            const uint32_t off = pf.first;
+            if (cp.key.path == 2) {
+                e = hipMemcpyAsync(nd->ptr + cp.off_wi + off * sizeof(int32_t), f->d_wq,
+                                   n3 * sizeof(uint32_t), hipMemcpyDeviceToDevice, stream);
+            } else {
+                e = hipMemcpyAsync(nd->ptr + cp.off_wf + off * sizeof(float), f->d_wf,
+                                   n3 * sizeof(float), hipMemcpyDeviceToDevice, stream);
+                if (e == hipSuccess && f->d_wi)
+                    e = hipMemcpyAsync(nd->ptr + cp.off_wi + off * sizeof(int32_t), f->d_wi,
+                                       n3 * sizeof(int32_t), hipMemcpyDeviceToDevice, stream);
+            }
+            if (e != hipSuccess) break;
+        }
+        cp.nitems = (uint32_t)items[i].size();
+        cp.args.vols = reinterpret_cast<const VolDesc*>(nd->ptr + cp.off_desc);
+        cp.args.items = reinterpret_cast<const WorkItem*>(nd->ptr + cp.off_items);
+        cp.args.nitems = cp.nitems;
+        cp.args.counters = reinterpret_cast<uint32_t*>(nd->ptr + cp.off_cnt);
+        cp.args.wpool = reinterpret_cast<const float*>(nd->ptr + cp.off_wf);
+        cp.args.wipool = reinterpret_cast<const int32_t*>(nd->ptr + cp.off_wi);
+        if (cp.grid > cp.nitems) cp.grid = cp.nitems > 0 ? cp.nitems : 1;
+        if (e == hipSuccess) e = launch_class(cp, stream);
+    }
+    return from_hip(e);
+}
+
 }  // namespace
 }  // namespace vkt
 
@@ -533,6 +681,22 @@ vktError vktApplyFilterBatched(int32_t n, const vktStructuredVolume* dst,
     hipError_t e = hipGraphLaunch(plan->exec, stream);
     if (e == hipSuccess) e = hipEventRecord(plan->done, stream);
     return from_hip(e);
+}
+
+vktError vktApplyFilterBatchedNoAlloc(int32_t n, const vktStructuredVolume* dst,
+                                      const vktStructuredVolume* src, const vktFilter* filters,
+                                      vktAddressMode mode)
+{
+    using namespace vkt;
+    if (n < 0 || (n > 0 && (!dst || !src || !filters))) return vktInvalidValue;
+    if (n == 0) return vktNoError;
+    hipStream_t stream = thread_stream();
+    std::vector<Triple> tr;
+    std::vector<uintptr_t> sig;
+    const vktError ve =
+        prepare_batch(n, dst, src, filters, mode, thread_precision(), stream, tr, sig);
+    if (ve != vktNoError) return ve;
+    return batched_no_alloc(tr, stream);
 }
 
 }  // extern "C"

@@ -55,6 +55,7 @@ SIGNATURES = {
     "vktApplyFilter": [_P, _P, _P, ctypes.c_int],
     "vktApplyFilterRange": [_P, _P, _P, _I32, _I32, _I32, _I32, _I32, _I32, ctypes.c_int],
     "vktApplyFilterBatched": [_I32, _PP, _PP, _PP, ctypes.c_int],
+    "vktApplyFilterBatchedNoAlloc": [_I32, _PP, _PP, _PP, ctypes.c_int],
     "vktBrickDecomposeGetNumBricks": [_P, _I32, _I32, _I32, _PI, _PI, _PI],
     "vktBrickDecomposeGetBrickDims": [_P, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _I32,
                                       _PI, _PI, _PI],
@@ -233,6 +234,17 @@ def vktApplyFilterBatched(dsts, srcs, filts, mode=vktAddressModeClamp):
     m = MODES[mode] if isinstance(mode, str) else int(mode)
     _ok(lib().vktApplyFilterBatched(n, arr(*dsts), arr(*srcs), arr(*filts), m),
         "vktApplyFilterBatched")
+
+
+def vktApplyFilterBatchedNoAlloc(dsts, srcs, filts, mode=vktAddressModeClamp):
+    """As vktApplyFilterBatched, with no device allocation (static scratch)."""
+    n = len(dsts)
+    if len(srcs) != n or len(filts) != n:
+        raise ValueError("batched call needs equal-length handle lists")
+    arr = ctypes.c_void_p * max(n, 1)
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    _ok(lib().vktApplyFilterBatchedNoAlloc(n, arr(*dsts), arr(*srcs), arr(*filts), m),
+        "vktApplyFilterBatchedNoAlloc")
 
 
 def vktResample(dst, src):
