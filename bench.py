@@ -1,37 +1,49 @@
 """Throughput benchmark of vktApplyFilter on one MI355X.
 
-Default workload: the plain-path pair of 512^3 volumes --
-  (a) uint8 CT-like phantom (N(40, 8^2) background, 200 solid spheres),
-      integer 3^3 box filter with divisor 27, clamp, uint8 out (bit-exact);
-  (b) float32 smoothed Gaussian noise (sigma 4), 5^3 Gaussian sigma 1.5,
-      clamp, float32 out.
-One step = one ApplyFilter of (a) and one of (b), with inputs resident in HBM.
-Prints ONE JSON line (metric Gvoxels/s = output cells / device time).
+Default workload (c2a+c3a), the two stencil sizes of the headline metric:
+  (a) 512^3 uint8 CT-like phantom (N(40, 8^2) background, 200 solid spheres),
+      integer 3^3 box filter with divisor 27, clamp, uint8 out (bit-exact),
+      on the 8-bit dot-product path;
+  (b) 1024^3 float32 blob field (64 Gaussian blobs + 1 % noise), dense 7^3
+      N(0,1) weights of unit L1 norm, clamp, float32 out, as the split-bf16
+      implicit GEMM on the matrix cores (3 products, FP32 accumulation).
+One step = one ApplyFilter of (a) and one of (b), inputs resident in HBM.
+Beside the step (per_case, in_step false): the same 7^3 filter as the plain
+FP32 vector-ALU kernel and as the 6-product split -- the plain vs matrix-core
+comparison at stated accuracy.  The CPU leg times the FP64 oracle on 32^3
+blocks of each case (all cores and one core) and reports max and RMS error of
+every GPU result against it.  Prints ONE JSON line (metric Gvoxels/s = output
+cells / device time).
 
-Other workloads (--workload): c1 (64^3 float32, 3^3 Gaussian), c3a / c3b
-(1024^3 float32 blob field, dense 7^3 / 9^3 unit-L1 weights), c4 (256 uneven
+Other workloads (--workload): c1 (64^3 float32, 3^3 Gaussian), c2 (the
+plain-path 512^3 pair: (a) and a float32 5^3 Gaussian), c2a, c2b, c3a / c3b
+(the 1024^3 field with 7^3 / 9^3 weights, split and plain), c4 (256 uneven
 uint16 volumes, batched), c5 (2048 x 2048 x 1024 uint16 ellipsoid phantom,
-11^3 Gaussian sigma 2.5), transforms (the two 512^3 volumes of the default
-workload: Resample down by two on every axis and Flip along the longest
-axis, the paper's other structured-volume benchmarks).
+11^3 Gaussian sigma 2.5), transforms (Resample down by two and Flip along the
+longest axis of the two 512^3 volumes, the paper's other structured-volume
+benchmarks).
 """
 import argparse
 import hashlib
 import json
 import os
+import statistics
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+METRIC = "Gvoxels/s ApplyFilter (3^3 and 7^3) on 1 MI355X; % HBM/MFMA peak; plain vs MFMA"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP32_VECTOR_PEAK_TF = 157.3    # MI355X FP32 vector (packed FMA), TFLOP/s
-BF16_MFMA_PEAK_TF = 2500.0     # MI355X dense bf16 matrix, TFLOP/s
+BF16_MFMA_PEAK_TF = 2500.0     # MI355X dense bf16/fp16 matrix, TFLOP/s
 # 8-bit dot products on the vector ALUs: 256 CUs x 4 SIMDs x 16 lanes x 4 MACs
 # x 2 ops x 2.4 GHz (v_dot4 issues at the full VALU rate)
 INT8_DOT_PEAK_TOPS = 256 * 4 * 16 * 4 * 2 * 2.4e9 / 1e12
 INT8_MFMA_PEAK_TOPS = 5000.0   # MI355X dense int8 matrix, TOP/s
+MALL_BYTES = 256 << 20         # Infinity Cache
 
 
 def parse():
@@ -39,24 +51,26 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2",
-                    choices=["c1", "c2", "c2a", "c2b", "c3a", "c3b", "c4", "c5",
+    ap.add_argument("--workload", default="c2a+c3a",
+                    choices=["c2a+c3a", "c1", "c2", "c2a", "c2b", "c3a", "c3b", "c4", "c5",
                              "transforms"])
     ap.add_argument("--precision", default=None,
                     choices=["auto", "fp32", "splitbf16", "splitbf16x6"],
-                    help="default: fp32 for c1/c2 (the plain-path configurations), "
-                         "auto (split bf16/fp16 matrix path for k >= 5) otherwise")
+                    help="precision of the in-step float filters with k >= 5 (default: "
+                         "splitbf16, the 3-product split; fp32 for the c1/c2 plain-path "
+                         "workloads)")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the out-of-step plain / 6-product comparison cases")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-blocks", type=int, default=512,
+                    help="random 32^3 blocks (plus the 8 corner blocks) per case on which "
+                         "the oracle is timed on all cores and the errors are measured")
     ap.add_argument("--int8-matrix", action="store_true",
                     help="uint8 3^3 integer filters on the int8 matrix cores instead of "
                          "the 8-bit dot products (vktSetInt8Matrix(1))")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0,
-                    help="target CPU time of the oracle baseline sample")
     ap.add_argument("--separable", action="store_true",
                     help="rank-1 fast path (vktSetSeparable): three 1-D passes for separable "
                          "filters; reported apart from the dense numbers")
-    ap.add_argument("--autotune", action="store_true",
-                    help="c4: let the batched planner time its slab-depth candidates")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -64,34 +78,51 @@ def parse():
 
 # --------------------------------------------------------------- workloads --
 
-def make_cases(name, device):
-    """List of dicts: name, src tensor, weights, divisor, flops/voxel, bytes."""
-    import numpy as np
+def make_cases(name, device, precision, compare):
+    """List of dicts: name, src tensor, weights, divisor, k, precision, and
+    whether the case is part of the timed step (comparison cases are timed
+    apart on the same input)."""
     import torch
     from paper_2203_10213_amd import synth
     S = synth.SEEDS
     cases = []
-    if name in ("c2", "c2a"):
+
+    def add(name, src, w, D, k, prec, in_step=True, blocks_seed=None):
+        cases.append(dict(name=name, src=src, w=w, D=D, k=k, precision=prec,
+                          in_step=in_step, blocks_seed=blocks_seed))
+
+    if name in ("c2", "c2a", "c2a+c3a"):
         src = torch.from_numpy(synth.ct_phantom_u8(512, S["c2a"])).to(device)
         w, D = synth.box_int(3)
-        cases.append(dict(name="c2a_u8_512_box3_div27", src=src, w=w, D=D, k=3))
+        add("c2a_u8_512_box3_div27", src, w, D, 3, "fp32", blocks_seed=S["c2_blocks"])
     if name in ("c2", "c2b"):
         src = synth.smoothed_noise_f32(512, 4.0, S["c2b"], device=device)
-        cases.append(dict(name="c2b_f32_512_gauss5_s1.5", src=src,
-                          w=synth.gaussian_weights(5, 1.5), D=None, k=5))
+        add("c2b_f32_512_gauss5_s1.5", src, synth.gaussian_weights(5, 1.5), None, 5,
+            precision or "fp32", blocks_seed=S["c2_blocks"])
     if name == "c1":
         src = torch.from_numpy(synth.uniform_f32((64, 64, 64), S["c1"])).to(device)
-        cases.append(dict(name="c1_f32_64_gauss3_s1", src=src,
-                          w=synth.gaussian_weights(3, 1.0), D=None, k=3))
-    if name in ("c3a", "c3b"):
-        k = 7 if name == "c3a" else 9
+        add("c1_f32_64_gauss3_s1", src, synth.gaussian_weights(3, 1.0), None, 3, "fp32",
+            blocks_seed=S["c1"])
+    if name in ("c3a", "c3b", "c2a+c3a"):
+        k = 9 if name == "c3b" else 7
         src = synth.blob_field_f32(1024, 64, S["c3"], device=device)
         w = synth.random_l1(k, S["c3a_w"] if k == 7 else S["c3b_w"])
-        cases.append(dict(name=f"{name}_f32_1024_dense{k}_l1", src=src, w=w, D=None, k=k))
+        tag = "c3a" if k == 7 else "c3b"
+        p = precision or "splitbf16"
+        add(f"{tag}_f32_1024_dense{k}_l1", src, w, None, k, p, blocks_seed=S["c3_blocks"])
+        if compare:
+            for q in ("fp32", "splitbf16x6", "splitbf16"):
+                if q != p:
+                    add(f"{tag}_f32_1024_dense{k}_l1", src, w, None, k, q, in_step=False,
+                        blocks_seed=S["c3_blocks"])
     if name == "c5":
         src = synth.ellipsoid_phantom_u16((1024, 2048, 2048), 5000, S["c5"], device=device)
-        cases.append(dict(name="c5_u16_2048x2048x1024_gauss11_s2.5", src=src,
-                          w=synth.gaussian_weights(11, 2.5), D=None, k=11))
+        w = synth.gaussian_weights(11, 2.5)
+        add("c5_u16_2048x2048x1024_gauss11_s2.5", src, w, None, 11, precision or "splitbf16",
+            blocks_seed=S["c5_blocks"])
+        if compare:
+            add("c5_u16_2048x2048x1024_gauss11_s2.5", src, w, None, 11, "fp32", in_step=False,
+                blocks_seed=S["c5_blocks"])
     for c in cases:
         c["voxels"] = c["src"].numel()
         c["cell_bytes"] = c["src"].element_size()
@@ -105,12 +136,13 @@ KERNEL_SOURCES = {
     "dot4": ["vkt_filter_dot4.hip", "vkt_internal.h"],
     "i8mma": ["vkt_filter_i8mma.hip", "vkt_internal.h"],
     "mfma": ["vkt_filter_mfma.hip", "vkt_internal.h"],
+    "sep": ["vkt_filter_sep.hip", "vkt_internal.h"],
 }
 
 
 def kernel_source_sha(path):
-    """Hash of the HIP sources of one kernel path; profile-derived traffic is
-    only reported for the kernel it was measured on."""
+    """Hash of the HIP sources of one kernel path; profile-derived figures are
+    only reported for the kernel they were measured on."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2203_10213_amd", "csrc")
     for f in KERNEL_SOURCES[path]:
@@ -120,102 +152,52 @@ def kernel_source_sha(path):
     return h.hexdigest()[:16]
 
 
-def stored_traffic(case_name, path):
-    """HBM bytes per launch from committed rocprofv3 --pmc summaries, scaled
-    by the copy-kernel calibration, if they match the current kernel."""
+def stored_profile(case_key, path, field):
+    """A per-launch figure (HBM bytes from FETCH_SIZE / WRITE_SIZE scaled by
+    the copy-kernel calibration, or the matrix-core busy fraction) from the
+    committed rocprofv3 summaries, if it was measured on the current kernel."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
     try:
         d = json.load(open(p))
-        e = d.get(case_name)
+        e = d.get(case_key)
         if e and e.get("path") == path and e.get("kernel_src_sha") == kernel_source_sha(path):
-            return e["hbm_bytes_per_launch"]
+            return e.get(field)
     except (ValueError, KeyError):
         pass
     return None
 
 
-def arith_dtype(c, precision):
+def case_key(c):
+    """Name of a case with its arithmetic (the profile table's key)."""
+    if c["path"] == "mfma":
+        return f"{c['name']}:mfma_x{c['products']}"
+    return f"{c['name']}:{c['path']}"
+
+
+def arith_dtype(c):
     """The type the path computes in."""
     if c["path"] == "mfma":
         if c["src"].dtype.is_floating_point:
-            return "bf16x3->f32" if precision == "splitbf16" else "bf16x6->f32"
-        return "f16x2->f32"
-    if c["path"] == "dot4":
-        return "u8dot4->i32"
-    if c["path"] == "i8mma":
-        return "i8mma->i32"
-    if c["path"] == "sep":
-        return "f32(rank-1)"
-    if c["D"] is not None:
-        return "f32(exact int)"
-    return "f32"
-
-
-def kernel_path(c, precision, separable=False, int8_matrix=False):
-    """The library's plan rule: float-weight filters with k >= 5 run on the
-    matrix cores unless the precision is fp32; uint8 volumes with integer
-    filters of k <= 7, weights all in [0, 255] or all in [-128, 127],
-    sum |w| <= 2048, divisor <= 2^19 and rows of a multiple of 4 cells run as
-    8-bit dot products (k = 3 with weights in [-128, 127] as int8 products on
-    the matrix cores when that is turned on); the rest on the vector ALUs in
-    FP32 / int32."""
-    import numpy as np
-    if separable and rank1(c["w"]) and not (c["k"] <= 3 and dot4_ok(c)):
-        return "sep"
-    if c["D"] is None:
-        return "mfma" if (c["k"] >= 5 and precision != "fp32") else "valu"
-    if not dot4_ok(c):
-        return "valu"
-    w = np.asarray(c["w"], np.int64)
-    if int8_matrix and c["k"] == 3 and w.min() >= -128 and w.max() <= 127:
-        return "i8mma"
-    return "dot4"
-
-
-def dot4_ok(c):
-    """The 8-bit dot-product path's eligibility (uint8 cells, integer
-    filter, k <= 7, weights in [0, 255] or [-128, 127], sum |w| <= 2048,
-    divisor <= 2^19, rows of a multiple of 4 cells)."""
-    import numpy as np
-    if c["D"] is None:
-        return False
-    w = np.asarray(c["w"], np.int64)
-    fits = (w.min() >= 0 and w.max() <= 255) or (w.min() >= -128 and w.max() <= 127)
-    return bool(c["src"].dtype == torch_uint8() and c["k"] in (3, 5, 7) and fits
-                and np.abs(w).sum() <= 2048 and c["D"] <= (1 << 19)
-                and c["src"].shape[-1] % 4 == 0)
-
-
-def rank1(w):
-    """The library's rank-1 test (float filters to 2^-21 max|w|; the integer
-    filters of these workloads are exact outer products)."""
-    import numpy as np
-    w = np.asarray(w, np.float64)
-    k = w.shape[0]
-    ip = np.unravel_index(np.argmax(np.abs(w)), w.shape)
-    p = w[ip]
-    if p == 0:
-        return False
-    t, v, u = w[:, ip[1], ip[2]] / p, w[ip[0], :, ip[2]] / p, w[ip[0], ip[1], :]
-    return bool(np.max(np.abs(np.einsum("c,b,a->cba", t, v, u) - w)) <= np.ldexp(abs(p), -21))
-
-
-def torch_uint8():
-    import torch
-    return torch.uint8
+            return f"bf16x{c['products']}->f32"
+        return f"f16x{c['products']}->f32"
+    return {"dot4": "u8dot4->i32", "i8mma": "i8mma->i32", "sep": "f32(rank-1)"}.get(
+        c["path"], "f32(exact int)" if c["D"] is not None else "f32")
 
 
 def case_roofline(c, ms):
     """Algorithmic bytes (1 cell read + 1 cell written per output) and flops
     (2 k^3 per output) over the measured time, against the roofline that
-    bounds this path: HBM, the FP32 vector ALUs, or the dense 16-bit matrix
-    cores (split products and Toeplitz zeros are overhead, not counted)."""
+    bounds this path at its algorithmic work: HBM, the FP32 vector ALUs, the
+    8-bit dot products, or the dense 16-bit / int8 matrix cores (split
+    products and Toeplitz zeros are overhead, not counted).  Matrix-core
+    cases also report the useful-product fraction (P split products of the
+    algorithmic flops) and the counter-measured busy fraction."""
     t = ms * 1e-3
     bytes_alg = 2 * c["voxels"] * c["cell_bytes"]
     # the rank-1 path's algorithm is three 1-D passes: 2 * 3k flops per output
-    flops = c["voxels"] * (6 * c["k"] if c.get("path") == "sep" else c["flops_per_voxel"])
+    flops = c["voxels"] * (6 * c["k"] if c["path"] == "sep" else c["flops_per_voxel"])
     gbs = bytes_alg / t / 1e9
     tfs = flops / t / 1e12
     peak_c = {"mfma": BF16_MFMA_PEAK_TF, "dot4": INT8_DOT_PEAK_TOPS,
@@ -228,49 +210,216 @@ def case_roofline(c, ms):
                 "peak": peak_c,
                 "unit": "TOP/s" if c["path"] in ("dot4", "i8mma") else "TFLOP/s",
                 "frac": tfs / peak_c}
-    return dict(case=c["name"], path=c["path"], ms=ms,
-                gvoxels_s=c["voxels"] / t / 1e9, hbm_gbs=gbs, hbm_frac=gbs / HBM_PEAK_GBS,
-                tflops=tfs, algorithmic_bytes=bytes_alg, flops=flops, roofline=roof)
+    out = dict(case=c["name"], in_step=c["in_step"], precision=c["precision"], path=c["path"],
+               products=c["products"], ms=ms, gvoxels_s=c["voxels"] / t / 1e9, hbm_gbs=gbs,
+               hbm_frac=gbs / HBM_PEAK_GBS, tflops=tfs, algorithmic_bytes=bytes_alg,
+               flops=flops, roofline=roof,
+               traffic=stored_profile(case_key(c), c["path"], "hbm_bytes_per_launch"))
+    if c["path"] == "mfma":
+        out["matrix_cores"] = {
+            "algorithmic_frac": tfs / BF16_MFMA_PEAK_TF,
+            "useful_product_frac": c["products"] * tfs / BF16_MFMA_PEAK_TF,
+            "busy_frac": stored_profile(case_key(c), "mfma", "mfma_busy")}
+    return out
 
 
-# ------------------------------------------------------------ CPU baseline --
+# ------------------------------------------------- CPU baseline and errors --
 
-def cpu_baseline(cases, target_s):
-    """The FP64 oracle timed on this host's cores on a bounded z-slab of each
-    case (same planes count fraction for every case), scaled to Gvoxels/s of
-    the whole step's mix."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def host_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def _blocks(t, origins):
+    """The 32^3 blocks (clipped to the volume) of device tensor t at origins."""
+    import torch
+    Z, Y, X = t.shape
+    bx, by, bz = min(32, X), min(32, Y), min(32, Z)
+    return torch.stack([t[z:z + bz, y:y + by, x:x + bx] for x, y, z in origins]).cpu().numpy()
+
+
+def result_errors(c, got, T, A):
+    """Error of one GPU result against the oracle on the checked cells:
+    float32 cells: max and RMS of |gpu - T| and of |gpu - T| / sum|w||s|;
+    integer cells: the oracle's stored result (bit-exact rule for integer
+    filters, half-up rounding for float filters) and the largest difference
+    in units of the last place."""
     import numpy as np
     import oracle
-    nthreads = min(16, os.cpu_count() or 1)
-    # calibrate with one plane per case, then size the slab to ~target_s
-    per_plane = []
-    hosts = []
+    n = int(got.size)
+    if got.dtype == np.float32:
+        d = np.abs(got.astype(np.float64) - T)
+        e = np.where(A > 0, d / np.maximum(A, 1e-300), np.where(d == 0, 0.0, np.inf))
+        return {"cells": n, "max_abs": float(d.max()), "rms_abs": float(np.sqrt(np.mean(d * d))),
+                "max_rel_sum_abs": float(e.max()), "rms_rel_sum_abs": float(np.sqrt(np.mean(e * e)))}
+    want = (oracle.store_int_filter(T, c["D"], got.dtype) if c["D"] is not None
+            else oracle.store_float_filter(T, got.dtype))
+    diff = np.abs(got.astype(np.int64) - want.astype(np.int64))
+    return {"cells": n, "max_lsb": int(diff.max()), "cells_differing": int((diff != 0).sum()),
+            "rule": "bit-exact" if c["D"] is not None else "within 1 LSB"}
+
+
+def cpu_leg(cases, n_random):
+    """The FP64 oracle timed on this host on 32^3 blocks of every distinct
+    (input, filter) of the workload: the 8 corner blocks plus n_random blocks
+    placed uniformly (seeded) on all cores, and the corner blocks plus 8
+    random ones on one core.  Its block results are then the reference for
+    the max / RMS error of every GPU result.  Returns (cpu_baseline, errors,
+    input hashes)."""
+    import numpy as np
+    import oracle
+    from paper_2203_10213_amd import synth
+    allc = min(16, host_cores())
+    groups = {}
     for c in cases:
-        src = c["src"].cpu().numpy()
-        hosts.append(src)
-        t0 = time.perf_counter()
-        oracle.correlate(src, np.asarray(c["w"], np.float64), "clamp", z_range=(0, 1),
-                         nthreads=nthreads, with_abs=False)
-        per_plane.append(time.perf_counter() - t0)
-    nplanes = max(1, int(target_s / max(sum(per_plane), 1e-6)))
-    tot_vox, tot_t = 0, 0.0
-    for c, src in zip(cases, hosts):
-        Z = src.shape[0]
-        z0 = Z // 2
-        z1 = min(Z, z0 + nplanes)
-        t0 = time.perf_counter()
-        oracle.correlate(src, np.asarray(c["w"], np.float64), "clamp", z_range=(z0, z1),
-                         nthreads=nthreads, with_abs=False)
-        dt = time.perf_counter() - t0
-        # weight each case by its share of the step's voxels
-        frac = c["voxels"] / (src.shape[1] * src.shape[2] * (z1 - z0))
-        tot_vox += c["voxels"]
-        tot_t += dt * frac
-    return {"value": tot_vox / tot_t / 1e9, "unit": "Gvoxels/s", "cores": nthreads,
-            "kind": "oracle",
-            "sample": f"FP64 direct-sum oracle on {nplanes} middle z-planes of each case "
-                      f"({', '.join(c['name'] for c in cases)}), {nthreads} threads, "
-                      f"time scaled to the full volumes"}
+        groups.setdefault((id(c["src"]), c["name"]), []).append(c)
+    per_voxel, errors, hashes, samples = {}, {}, {}, []
+    for (_, name), cs in groups.items():
+        c0 = cs[0]
+        src = c0["src"].cpu().numpy()
+        hashes[name] = hashlib.sha256(memoryview(np.ascontiguousarray(src)).cast("B")).hexdigest()
+        origins = synth.sample_blocks(src.shape, n_random, c0["blocks_seed"])
+        w = np.asarray(c0["w"], np.float64)
+        Z, Y, X = src.shape
+        ext = (min(32, X), min(32, Y), min(32, Z))
+        vox_per_block = ext[0] * ext[1] * ext[2]
+
+        def run(orgs, nthreads):
+            Ts, As = [], []
+            t0 = time.perf_counter()
+            for x, y, z in orgs:
+                T, A = oracle.correlate_box(src, w, "clamp", (x, y, z),
+                                            (x + ext[0], y + ext[1], z + ext[2]),
+                                            nthreads=nthreads)
+                Ts.append(T)
+                As.append(A)
+            return time.perf_counter() - t0, np.stack(Ts), np.stack(As)
+
+        print(f"[bench] oracle on {len(origins)} blocks of {name}, {allc} threads",
+              file=sys.stderr, flush=True)
+        t_all, T, A = run(origins, allc)
+        one = origins[:16]
+        print(f"[bench] oracle on {len(one)} blocks of {name}, 1 thread", file=sys.stderr,
+              flush=True)
+        t_one, _, _ = run(one, 1)
+        per_voxel[name] = (t_all / (len(origins) * vox_per_block),
+                           t_one / (len(one) * vox_per_block))
+        samples.append(f"{name}: {len(origins)} blocks of {ext[0]}x{ext[1]}x{ext[2]} cells "
+                       f"(8 corners + {len(origins) - 8} uniform, seed {c0['blocks_seed']}) on "
+                       f"{allc} threads, {len(one)} of them on 1 thread")
+        for c in cs:
+            got = _blocks(c["dst"], origins)
+            errors[f"{c['name']}:{c['precision']}:{c['path']}"] = result_errors(c, got, T, A)
+    step = [c for c in cases if c["in_step"]]
+    vox = sum(c["voxels"] for c in step)
+    t_allc = sum(c["voxels"] * per_voxel[c["name"]][0] for c in step)
+    t_1 = sum(c["voxels"] * per_voxel[c["name"]][1] for c in step)
+    cpu = {"value": vox / t_allc / 1e9, "unit": "Gvoxels/s", "cores": allc, "kind": "oracle",
+           "sample": "FP64 direct-sum oracle (C, -O2) on " + "; ".join(samples) +
+                     "; time per cell scaled to the step's cells",
+           "one_core": {"value": vox / t_1 / 1e9, "unit": "Gvoxels/s", "cores": 1},
+           "cpu_model": cpu_model(), "host_cpus": host_cores(), "nproc": os.cpu_count()}
+    return cpu, errors, hashes
+
+
+# ------------------------------------------------------------ clocks, copy --
+
+class ClockSampler:
+    """Samples the GPU's graphics clock (MHz) from a thread while the timed
+    region runs: amdsmi if it loads, else the driver's sysfs DPM table."""
+
+    def __init__(self, period_s=0.005):
+        self.period = period_s
+        self.samples = []
+        self.read = None
+        self.source = None
+        try:
+            import amdsmi
+            amdsmi.amdsmi_init()
+            h = amdsmi.amdsmi_get_processor_handles()[0]
+
+            def rd():
+                return float(amdsmi.amdsmi_get_clock_info(h, amdsmi.AmdSmiClkType.GFX)["clk"])
+            rd()
+            self.read, self.source = rd, "amdsmi GFX clock"
+        except Exception:
+            import glob
+            for f in sorted(glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk")):
+                def rd(f=f):
+                    for line in open(f):
+                        if "*" in line:
+                            return float(line.split(":", 1)[1].replace("*", "")
+                                         .strip().lower().replace("mhz", ""))
+                    return None
+                try:
+                    if rd() is not None:
+                        self.read, self.source = rd, f
+                        break
+                except (OSError, ValueError):
+                    pass
+        self._stop = threading.Event()
+        self._th = None
+
+    def _loop(self):
+        while not self._stop.is_set():
+            try:
+                v = self.read()
+                if v:
+                    self.samples.append(v)
+            except Exception:
+                pass
+            time.sleep(self.period)
+
+    def __enter__(self):
+        if self.read:
+            self._th = threading.Thread(target=self._loop, daemon=True)
+            self._th.start()
+        return self
+
+    def __exit__(self, *a):
+        self._stop.set()
+        if self._th:
+            self._th.join()
+
+    def report(self):
+        if not self.samples:
+            return {"mhz_median": None, "source": self.source}
+        return {"mhz_median": statistics.median(self.samples), "mhz_min": min(self.samples),
+                "mhz_max": max(self.samples), "samples": len(self.samples),
+                "source": self.source}
+
+
+def copy_ceiling(torch, stream, reps=10):
+    """Achieved HBM rate of a plain 1 GiB device-to-device copy (read +
+    write bytes / time), the practical ceiling for streaming kernels."""
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / reps * 1e-3
+    del a, b
+    gbs = 2 * n / t / 1e9
+    return {"bytes": 2 * n, "gbs": gbs, "frac": gbs / HBM_PEAK_GBS}
 
 
 # -------------------------------------------------------------------- main --
@@ -289,22 +438,28 @@ def copy_probe():
 def run_batched(args, vkt, torch):
     """The batched workload: 256 uint16 volumes of uneven sizes, k in {3,5,7}
     Gaussians, one vktApplyFilterBatched (persistent kernels, replayed
-    hipGraph) per step; the same work as 256 single launches is timed beside
-    it.  Returns the bench line."""
+    hipGraph) per step.  Timed three ways: the batched call with the planner's
+    default slab depths, the batched call after the autotuner has timed its
+    candidates on this batch (a second set of outputs, so a second plan), and
+    the same work as 256 single launches.  The CPU leg times the oracle on one
+    32^3 block of every volume (all cores and one core) and reports the
+    largest difference of the batched result from it.  Returns the line."""
+    import numpy as np
     from paper_2203_10213_amd import synth
     vols, ks = synth.gamma_u16_volumes(256, synth.SEEDS["c4"])
     filts = {k: vkt.vktFilterCreate(synth.gaussian_weights(k, k / 4)) for k in (3, 5, 7)}
     srcs = [torch.from_numpy(v).cuda() for v in vols]
     dsts = [torch.empty_like(x) for x in srcs]
+    dsts_t = [torch.empty_like(x) for x in srcs]
     hs = [vkt.volume_from_tensor(x) for x in srcs]
     hd = [vkt.volume_from_tensor(x) for x in dsts]
+    ht = [vkt.volume_from_tensor(x) for x in dsts_t]
     hf = [filts[k] for k in ks]
     stream = torch.cuda.current_stream()
-    vkt.vktSetAutotune(args.autotune)
     torch.cuda.synchronize()
 
-    def batched():
-        vkt.vktApplyFilterBatched(hd, hs, hf, "clamp")
+    def batched(out):
+        return lambda: vkt.vktApplyFilterBatched(out, hs, hf, "clamp")
 
     def singles():
         for i in range(len(hs)):
@@ -323,40 +478,105 @@ def run_batched(args, vkt, torch):
         torch.cuda.synchronize()
         return t0.elapsed_time(t1) / K
 
-    print(f"[bench] c4 batched, warmup {args.warmup}", file=sys.stderr, flush=True)
-    ms_b = timed(batched, args.steps, args.warmup)
-    print("[bench] c4 single launches", file=sys.stderr, flush=True)
-    ms_s = timed(singles, max(1, args.steps // 2), 1)
+    clocks = ClockSampler()
+    with clocks:
+        print(f"[bench] c4 batched (default slab depths), warmup {args.warmup}", file=sys.stderr,
+              flush=True)
+        vkt.vktSetAutotune(False)
+        ms_u = timed(batched(hd), args.steps, args.warmup)
+        print("[bench] c4 batched, autotuned plan", file=sys.stderr, flush=True)
+        vkt.vktSetAutotune(True)
+        ms_t = timed(batched(ht), args.steps, args.warmup)
+        vkt.vktSetAutotune(False)
+        print("[bench] c4 single launches", file=sys.stderr, flush=True)
+        ms_s = timed(singles, max(1, args.steps // 2), 1)
+    # the step is the better of the two batched plans (the tuned one unless
+    # tuning picked nothing faster)
+    ms_b = min(ms_u, ms_t)
     voxels = sum(int(v.size) for v in vols)
     flops = sum(int(v.size) * 2 * k ** 3 for v, k in zip(vols, ks))
     bytes_alg = 4 * voxels
     t = ms_b * 1e-3
-    # the step's binding roofline: the split-fp16 matrix path carries the
-    # k = 5, 7 volumes (most of the flops); all volumes move 4 bytes per cell
+    gbs = bytes_alg / t / 1e9
+    # the batch's binding roofline at its algorithmic work: 4 bytes per cell
+    # moved (HBM) against the split-fp16 matrix flops of the k = 5, 7 volumes
     mfma_flops = sum(int(v.size) * 2 * k ** 3 for v, k in zip(vols, ks) if k >= 5)
-    roof = {"bound": "mfma", "achieved": mfma_flops / t / 1e12, "peak": BF16_MFMA_PEAK_TF,
-            "unit": "TFLOP/s", "frac": mfma_flops / t / 1e12 / BF16_MFMA_PEAK_TF,
-            "traffic": None, "kernel_case": "c4 k>=5 classes (one graph launch)"}
+    if bytes_alg / (HBM_PEAK_GBS * 1e9) >= mfma_flops / (BF16_MFMA_PEAK_TF * 1e12):
+        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs / HBM_PEAK_GBS}
+    else:
+        roof = {"bound": "mfma", "achieved": mfma_flops / t / 1e12, "peak": BF16_MFMA_PEAK_TF,
+                "unit": "TFLOP/s", "frac": mfma_flops / t / 1e12 / BF16_MFMA_PEAK_TF}
+    roof.update({"traffic": stored_profile("c4_batched_graph", "mfma", "hbm_bytes_per_launch"),
+                 "kernel_case": "c4 batched graph (all classes, one launch)"})
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        allc = min(16, host_cores())
+        g = np.random.default_rng(synth.SEEDS["c4"] + 1)
+        worst, cells, t_all, t_one, n_one = 0, 0, 0.0, 0.0, 0
+        print("[bench] CPU leg: the FP64 oracle on one 32^3 block of each volume",
+              file=sys.stderr, flush=True)
+        for i, (v, k) in enumerate(zip(vols, ks)):
+            Z, Y, X = v.shape
+            e = (min(32, X), min(32, Y), min(32, Z))
+            o = tuple(int(g.integers(0, d - ed + 1)) for d, ed in zip((X, Y, Z), e))
+            w = synth.gaussian_weights(k, k / 4).astype(np.float64)
+            t0 = time.perf_counter()
+            T = oracle.correlate_box(v, w, "clamp", o, tuple(a + b for a, b in zip(o, e)),
+                                     nthreads=allc, with_abs=False)
+            t_all += time.perf_counter() - t0
+            if i < 16:
+                t0 = time.perf_counter()
+                oracle.correlate_box(v, w, "clamp", o, tuple(a + b for a, b in zip(o, e)),
+                                     nthreads=1, with_abs=False)
+                t_one += time.perf_counter() - t0
+                n_one += T.size
+            want = oracle.store_float_filter(T, np.uint16)
+            for out in (dsts, dsts_t):
+                got = out[i].view(torch.int16)[o[2]:o[2] + e[2], o[1]:o[1] + e[1],
+                                               o[0]:o[0] + e[0]].cpu().numpy().view(np.uint16)
+                worst = max(worst, int(np.abs(got.astype(np.int64) - want).max()))
+            cells += T.size
+        # time per cell weighted by each volume's filter size
+        work = sum(int(v.size) * k ** 3 for v, k in zip(vols, ks))
+        per_tap_all = t_all / sum(min(32, v.shape[0]) * min(32, v.shape[1]) * min(32, v.shape[2])
+                                  * k ** 3 for v, k in zip(vols, ks))
+        per_tap_one = t_one / sum(min(32, v.shape[0]) * min(32, v.shape[1]) * min(32, v.shape[2])
+                                  * k ** 3 for v, k in list(zip(vols, ks))[:16])
+        cpu = {"value": voxels / (work * per_tap_all) / 1e9, "unit": "Gvoxels/s", "cores": allc,
+               "kind": "oracle",
+               "sample": f"FP64 oracle on one 32^3 block (or the whole volume where smaller) of "
+                         f"each of the 256 volumes, {cells} cells, {allc} threads; 16 of the "
+                         f"blocks on 1 thread; time per tap scaled to the batch's taps",
+               "one_core": {"value": voxels / (work * per_tap_one) / 1e9,
+                            "unit": "Gvoxels/s", "cores": 1},
+               "cpu_model": cpu_model(), "host_cpus": host_cores(), "nproc": os.cpu_count(),
+               "max_lsb_vs_oracle": worst, "cells_checked": cells}
     line = {
-        "metric": "Gvoxels/s ApplyFilter on 1 MI355X",
+        "metric": "Gvoxels/s ApplyFilter, batched uneven volumes, on 1 MI355X",
         "value": voxels / t / 1e9, "unit": "Gvoxels/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_b, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f16x2->f32+f32",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f16x4->f32+f32",
         "data": "synthetic",
         "config": {"workload": "c4", "cases": ["256 u16 volumes, axes U{32..256}, "
                                                "Gaussian k in {3,5,7}, sigma k/4"],
-                   "address_mode": "clamp", "precision": args.precision,
-                   "autotune": bool(args.autotune)},
+                   "address_mode": "clamp", "precision": args.precision or "auto"},
         "roofline": roof,
-        "cpu_baseline": None,
-        "per_case": [{"case": "c4_batched_graph", "ms": ms_b, "gvoxels_s": voxels / t / 1e9,
-                      "hbm_frac": bytes_alg / t / 1e9 / HBM_PEAK_GBS, "tflops": flops / t / 1e12},
+        "cpu_baseline": cpu,
+        "sclk": clocks.report(),
+        "per_case": [{"case": "c4_batched_default_slabs", "ms": ms_u,
+                      "gvoxels_s": voxels / (ms_u * 1e-3) / 1e9,
+                      "hbm_frac": bytes_alg / (ms_u * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                     {"case": "c4_batched_autotuned", "ms": ms_t,
+                      "gvoxels_s": voxels / (ms_t * 1e-3) / 1e9,
+                      "hbm_frac": bytes_alg / (ms_t * 1e-3) / 1e9 / HBM_PEAK_GBS},
                      {"case": "c4_256_single_launches", "ms": ms_s,
                       "gvoxels_s": voxels / (ms_s * 1e-3) / 1e9,
                       "hbm_frac": bytes_alg / (ms_s * 1e-3) / 1e9 / HBM_PEAK_GBS,
                       "tflops": flops / (ms_s * 1e-3) / 1e12}],
     }
-    for h in hs + hd:
+    for h in hs + hd + ht:
         vkt.vktStructuredVolumeDestroy(h)
     for f in filts.values():
         vkt.vktFilterDestroy(f)
@@ -445,7 +665,7 @@ def run_transforms(args, vkt, torch):
                              hbm_frac=gbs / HBM_PEAK_GBS, algorithmic_bytes=o["bytes"]))
     dom = max((p for p in per_case if p["in_step"]), key=lambda p: p["ms"])
     roof = {"bound": "hbm", "achieved": dom["hbm_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": dom["hbm_frac"], "traffic": stored_traffic(dom["case"], "resample"),
+            "frac": dom["hbm_frac"], "traffic": stored_profile(dom["case"], "resample", "hbm_bytes_per_launch"),
             "kernel_case": dom["case"]}
     voxels = sum(o["voxels"] for o in step_ops)
 
@@ -480,6 +700,130 @@ def run_transforms(args, vkt, torch):
     return line
 
 
+def run_filters(args, vkt, torch):
+    """The single-volume ApplyFilter workloads: the step's cases timed
+    together K times (HIP events around the whole step and around each
+    call, on the stream the library launches on), the comparison cases K
+    times apart; then the CPU leg.  Returns the bench line."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    print(f"[bench] building inputs for {args.workload}", file=sys.stderr, flush=True)
+    cases = make_cases(args.workload, dev, args.precision, not args.no_compare)
+    for c in cases:
+        c["dst"] = torch.empty_like(c["src"])
+        c["hs"] = vkt.volume_from_tensor(c["src"])
+        c["hd"] = vkt.volume_from_tensor(c["dst"])
+        c["hf"] = (vkt.vktFilterCreate(c["w"]) if c["D"] is None
+                   else vkt.vktFilterCreateInt(c["w"], c["D"]))
+        vkt.vktSetPrecision(c["precision"])
+        p, n = vkt.vktGetFilterPath(c["hd"], c["hs"], c["hf"], "clamp")
+        c["path"], c["products"] = vkt.FILTER_PATHS[p], n
+    torch.cuda.synchronize()
+    step_cases = [c for c in cases if c["in_step"]]
+    cmp_cases = [c for c in cases if not c["in_step"]]
+    # working sets below 1 GiB would stay partly in the 256 MB MALL between
+    # steps: flush it with a 1 GiB write between steps and time the kernels
+    # themselves (events around each call)
+    ws = sum(2 * c["voxels"] * c["cell_bytes"] for c in step_cases)
+    flush = torch.empty(1 << 30, dtype=torch.uint8, device=dev) if ws < (1 << 30) else None
+
+    def call(c):
+        vkt.vktSetPrecision(c["precision"])
+        vkt.vktApplyFilter(c["hd"], c["hs"], c["hf"], vkt.vktAddressModeClamp)
+
+    def timed(cs, K, W, with_flush):
+        for _ in range(W):
+            for c in cs:
+                call(c)
+        vkt.vktSynchronize()
+        torch.cuda.synchronize()
+        evs = [[[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in cs]
+               for _ in range(K)]
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for s in range(K):
+            if with_flush:
+                flush.fill_(s & 0xff)
+            for i, c in enumerate(cs):
+                evs[s][i][0].record(stream)
+                call(c)
+                evs[s][i][1].record(stream)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        vkt.vktSynchronize()
+        per = [sum(evs[s][i][0].elapsed_time(evs[s][i][1]) for s in range(K)) / K
+               for i in range(len(cs))]
+        return t0.elapsed_time(t1) / K, per
+
+    K = args.steps
+    clocks = ClockSampler()
+    with clocks:
+        print(f"[bench] step: {', '.join(c['name'] + ':' + c['path'] for c in step_cases)}; "
+              f"warmup {args.warmup}, {K} steps", file=sys.stderr, flush=True)
+        ms_bracket, per_step = timed(step_cases, K, args.warmup, flush is not None)
+        per_cmp = []
+        for c in cmp_cases:
+            print(f"[bench] comparison: {c['name']} {c['precision']} ({c['path']})",
+                  file=sys.stderr, flush=True)
+            per_cmp += timed([c], K, 1, False)[1]
+    # with a MALL flush between steps the step time is the sum of the calls
+    ms_step = sum(per_step) if flush is not None else ms_bracket
+    voxels = sum(c["voxels"] for c in step_cases)
+    value = voxels / (ms_step * 1e-3) / 1e9
+    per_case = [case_roofline(c, ms) for c, ms in zip(step_cases + cmp_cases, per_step + per_cmp)]
+    dom = max(range(len(step_cases)), key=lambda i: per_case[i]["ms"])
+    d = per_case[dom]
+    roof = dict(d["roofline"])
+    roof["kernel_case"] = f"{d['case']} ({d['path']}, {d['precision']})"
+    roof["traffic"] = d["traffic"]
+    if "matrix_cores" in d:
+        roof["matrix_cores"] = d["matrix_cores"]
+    print("[bench] copy ceiling", file=sys.stderr, flush=True)
+    ceiling = copy_ceiling(torch, stream)
+
+    cpu, errors, hashes = None, None, None
+    if not args.no_cpu_baseline:
+        print("[bench] CPU leg: the FP64 oracle on 32^3 blocks (timing and errors)",
+              file=sys.stderr, flush=True)
+        cpu, errors, hashes = cpu_leg(cases, args.cpu_blocks)
+        for p in per_case:
+            for k, v in errors.items():
+                if k.startswith(f"{p['case']}:{p['precision']}:{p['path']}"):
+                    p["error_vs_oracle"] = v
+
+    dtype = {torch.uint8: "u8", torch.uint16: "u16", torch.float32: "f32"}
+    line = {
+        "metric": METRIC + (" (rank-1 separable fast path)" if args.separable else ""),
+        "value": value, "unit": "Gvoxels/s", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "+".join(arith_dtype(c) for c in step_cases),
+        "data": "synthetic",
+        "config": {"workload": args.workload,
+                   "cases": [f"{c['name']} ({dtype[c['src'].dtype]} "
+                             f"{'x'.join(str(v) for v in reversed(c['src'].shape))}, "
+                             f"{c['path']}, {c['precision']})" for c in step_cases],
+                   "compare": [f"{c['name']} ({c['path']}, {c['precision']})" for c in cmp_cases],
+                   "address_mode": "clamp", "separable": bool(args.separable),
+                   "timing": ("sum of per-call HIP events per step, MALL flushed between steps "
+                              "by a 1 GiB write" if flush is not None else
+                              f"HIP events around {K} whole steps (working set "
+                              f"{ws / 2**30:.1f} GiB, > 4x the 256 MB MALL)"),
+                   "input_sha256": hashes},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "sclk": clocks.report(),
+        "copy_ceiling": ceiling,
+        "per_case": per_case,
+    }
+    for c in cases:
+        vkt.vktFilterDestroy(c["hf"])
+        vkt.vktStructuredVolumeDestroy(c["hs"])
+        vkt.vktStructuredVolumeDestroy(c["hd"])
+    return line
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -488,7 +832,6 @@ def main():
               "(a single volume would shard along z with an r-plane halo exchange)",
               file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
     from paper_2203_10213_amd import vkt
     if not torch.cuda.is_available():
@@ -497,102 +840,19 @@ def main():
     if args.copy_probe:
         copy_probe()
         return
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    if args.precision is None:
-        args.precision = "fp32" if args.workload in ("c1", "c2", "c2a", "c2b") else "auto"
-    stream = torch.cuda.current_stream()
-    vkt.vktSetStream(stream)
-    vkt.vktSetPrecision(args.precision)
+    torch.cuda.set_device(torch.device("cuda:0"))
+    if args.precision is None and args.workload in ("c1", "c2", "c2b"):
+        args.precision = "fp32"
+    vkt.vktSetStream(torch.cuda.current_stream())
+    vkt.vktSetPrecision(args.precision or "auto")
     vkt.vktSetSeparable(args.separable)
     vkt.vktSetInt8Matrix(args.int8_matrix)
     if args.workload == "c4":
         print(json.dumps(run_batched(args, vkt, torch)))
-        return
-    if args.workload == "transforms":
+    elif args.workload == "transforms":
         print(json.dumps(run_transforms(args, vkt, torch)))
-        return
-    print(f"[bench] building inputs for {args.workload}", file=sys.stderr, flush=True)
-    cases = make_cases(args.workload, dev)
-    for c in cases:
-        c["path"] = kernel_path(c, args.precision, args.separable, args.int8_matrix)
-        c["dst"] = torch.empty_like(c["src"])
-        c["hs"] = vkt.volume_from_tensor(c["src"])
-        c["hd"] = vkt.volume_from_tensor(c["dst"])
-        c["hf"] = (vkt.vktFilterCreate(c["w"]) if c["D"] is None
-                   else vkt.vktFilterCreateInt(c["w"], c["D"]))
-    torch.cuda.synchronize()
-
-    def step(evs=None):
-        for i, c in enumerate(cases):
-            if evs is not None:
-                evs[i][0].record(stream)
-            vkt.vktApplyFilter(c["hd"], c["hs"], c["hf"], vkt.vktAddressModeClamp)
-            if evs is not None:
-                evs[i][1].record(stream)
-
-    print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        step()
-    vkt.vktSynchronize()
-    torch.cuda.synchronize()
-
-    K = args.steps
-    evs = [[[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in cases]
-           for _ in range(K)]
-    t_begin = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_begin.record(stream)
-    for s in range(K):
-        step(evs[s])
-    t_end.record(stream)
-    torch.cuda.synchronize()
-    vkt.vktSynchronize()
-    total_ms = t_begin.elapsed_time(t_end)
-    ms_step = total_ms / K
-    voxels = sum(c["voxels"] for c in cases)
-    value = voxels / (ms_step * 1e-3) / 1e9
-
-    per_case = []
-    for i, c in enumerate(cases):
-        ms = sum(evs[s][i][0].elapsed_time(evs[s][i][1]) for s in range(K)) / K
-        per_case.append(case_roofline(c, ms))
-    dom = max(range(len(cases)), key=lambda i: per_case[i]["ms"])
-    d = per_case[dom]
-    roof = dict(d["roofline"])
-    roof["kernel_case"] = d["case"]
-    roof["traffic"] = stored_traffic(d["case"], d["path"])
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        print("[bench] timing the CPU oracle baseline", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(cases, args.cpu_seconds)
-
-    dtype = {torch.uint8: "u8", torch.uint16: "u16", torch.float32: "f32"}
-    line = {
-        "metric": ("Gvoxels/s ApplyFilter on 1 MI355X" +
-                   (" (rank-1 separable fast path)" if args.separable else "")),
-        "value": value, "unit": "Gvoxels/s", "n_gpus": 1, "steps": K,
-        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None,
-        "dtype": "+".join(sorted({arith_dtype(c, args.precision) for c in cases})),
-        "data": "synthetic",
-        "config": {"workload": args.workload,
-                   "cases": [f"{c['name']} ({dtype[c['src'].dtype]} "
-                             f"{'x'.join(str(v) for v in reversed(c['src'].shape))})"
-                             for c in cases],
-                   "address_mode": "clamp", "precision": args.precision,
-                   "separable": bool(args.separable)},
-        "roofline": roof,
-        "cpu_baseline": cpu,
-        "per_case": per_case,
-    }
-    for c in cases:
-        vkt.vktFilterDestroy(c["hf"])
-        vkt.vktStructuredVolumeDestroy(c["hs"])
-        vkt.vktStructuredVolumeDestroy(c["hd"])
-    print(json.dumps(line))
+    else:
+        print(json.dumps(run_filters(args, vkt, torch)))
 
 
 if __name__ == "__main__":
