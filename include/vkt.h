@@ -205,9 +205,12 @@ vktError vktApplyFilterRange(vktStructuredVolume dst, vktStructuredVolume src,
  * dims, filter identities, mode, precision and stream -- so a repeated batch
  * is one graph launch.  Outputs must not overlap any volume of the batch.
  * Two calls with the same signature must not run concurrently (they share
- * the plan's work queue).  With vktSetAutotune(1) the first plan of a batch
- * size class times candidate z-slab depths per class on the real data (this
- * writes the outputs and waits for the stream) and records the fastest;
+ * the plan's work queue).  Calls from several threads are serialised inside
+ * the library (planning, graph instantiation and launch run one call at a
+ * time; the enqueued work runs concurrently on the callers' streams).  With vktSetAutotune(1) the first plan of a batch
+ * size class times, per class, both tile heights of the class kernel at
+ * candidate z-slab depths on the real data (this writes the outputs and
+ * waits for the stream) and records the fastest tile and depth;
  * VKT_TUNE_CACHE=<file> keeps that table across processes.
  * Errors: as vktApplyFilter for any pair; vktInvalidValue for n < 0, NULL
  * arrays or overlapping outputs; vktOutOfMemory for the plan buffer. */
@@ -251,9 +254,11 @@ vktError vktApplyFilterBatchedNoAlloc(int32_t n, const vktStructuredVolume* dst,
  * edge cell).  Stored as the FP32 value (Float32) or rounded half-up and
  * saturated (UInt8/UInt16).  When every src dim is twice the dst dim the
  * result is the mean of each 2x2x2 block, exact for integer formats
- * ((sum + 4) / 8, truncated).  Other sizes interpolate in FP32 with
- * positions formed in FP64: Float32 within a few FP32 roundings of the
- * largest neighbour, integer formats within 1 of the exact rounding.
+ * ((sum + 4) / 8, truncated).  Other sizes interpolate in FP32, the
+ * sample positions split exactly (integer arithmetic) into cell and
+ * fraction, the fraction rounded once to FP32: Float32 within a few FP32
+ * roundings of the largest neighbour, integer formats within 1 of the exact
+ * rounding.
  * Errors: vktInvalidValue for bad handles, different formats or overlapping
  * buffers. */
 vktError vktResample(vktStructuredVolume dst, vktStructuredVolume src);
@@ -324,8 +329,10 @@ vktError vktSetAutotune(int enable);
 
 /* Rank-1 fast path (opt-in, per thread; default: the VKT_SEPARABLE
  * environment variable, "1" enables).  A filter whose weights factor as
- * w[c][b][a] = t[c] v[b] u[a] -- exactly for integer filters, to within
- * 2^-21 max|w| for float filters -- then runs as three one-dimensional
+ * w[c][b][a] = t[c] v[b] u[a] -- exactly for integer filters; for float
+ * filters every weight to within 2^-20 of itself (so the three passes stay
+ * within about 2^-20 sum|w||s| of the dense sum, plus their own FP32
+ * rounding) -- then runs as three one-dimensional
  * passes (3k instead of k^3 multiply-adds per cell, FP32 arithmetic), in
  * vktApplyFilter and vktApplyFilterRange.  Integer filters on integer
  * formats take it only while every partial sum stays an exact integer in

@@ -6,9 +6,11 @@
 //     vktApplyFilter; triples fall into arithmetic classes (cell format, k,
 //     vector-ALU or matrix-core path and its variant), one persistent kernel
 //     per class;
-//   * each volume is cut into tile-slabs (the kernels' output tiles times a
-//     z-slab depth chosen per class and batch size class, optionally by the
-//     autotuner); the class's work list is sorted longest first;
+//   * each volume is cut into tile-slabs (the kernel's output tile -- one of
+//     two tile heights -- times a z-slab depth, both chosen per class and
+//     batch size class, by default or by the autotuner, which times every
+//     tile height at candidate depths on the real batch); the class's work
+//     list is sorted longest first;
 //   * descriptors, work lists, the classes' weight pools and the work-queue
 //     counters go to one device buffer; the class kernels become parallel
 //     kernel nodes of one hipGraph.
@@ -41,24 +43,27 @@ struct ClassKey {
     }
 };
 
-const void* class_kernel(const ClassKey& c)
+// variant: the class's tile-height variant (0: default tile, 1: the other
+// height; kTileVariants in all)
+const void* class_kernel(const ClassKey& c, int variant)
 {
-    if (c.path == 2) return dot4_batched_kernel(c.k, c.flag != 0);
-    return c.path ? mfma_batched_kernel((vktDataFormat)c.fmt, c.k, c.flag != 0)
-                  : valu_batched_kernel((vktDataFormat)c.fmt, c.k, c.flag != 0);
+    if (c.path == 2) return dot4_batched_kernel(c.k, c.flag != 0, variant);
+    return c.path ? mfma_batched_kernel((vktDataFormat)c.fmt, c.k, c.flag != 0, variant)
+                  : valu_batched_kernel((vktDataFormat)c.fmt, c.k, c.flag != 0, variant);
 }
 
-ClassGeom class_geom(const ClassKey& c)
+ClassGeom class_geom(const ClassKey& c, int variant)
 {
-    if (c.path == 2) return dot4_geom(c.k);
-    return c.path ? mfma_geom((vktDataFormat)c.fmt, c.k, c.flag != 0) : valu_geom(c.k);
+    if (c.path == 2) return dot4_geom(c.k, variant);
+    return c.path ? mfma_geom((vktDataFormat)c.fmt, c.k, c.flag != 0, variant)
+                  : valu_geom(c.k, variant);
 }
 
 // Weights per filter in the class's pools: k^3 (float and int pools), or the
 // packed 8-bit rows (int pool) of the dot-product path.
 int class_weights(const ClassKey& c) { return c.path == 2 ? dot4_words(c.k) : c.k * c.k * c.k; }
 
-// ---- tuning table: (class, size class) -> z-slab depth ---------------------
+// ---- tuning table: (class, size class) -> tile variant and z-slab depth ----
 
 struct TuneKey {
     ClassKey c;
@@ -69,8 +74,13 @@ struct TuneKey {
     }
 };
 
+struct TuneVal {
+    int tz;        // z-slab depth (0: no entry)
+    int variant;   // tile-height variant
+};
+
 std::mutex g_tune_mu;
-std::map<TuneKey, int> g_tune;
+std::map<TuneKey, TuneVal> g_tune;
 bool g_tune_loaded = false;
 
 // Size class of a set of volumes: log2 of the mean cube-root edge length.
@@ -89,11 +99,15 @@ void tune_load_locked()
     if (!path) return;
     FILE* f = std::fopen(path, "r");
     if (!f) return;
-    TuneKey k;
-    int tz;
-    while (std::fscanf(f, "%d %d %d %d %d %d", &k.c.fmt, &k.c.k, &k.c.path, &k.c.flag,
-                       &k.size_class, &tz) == 6)
-        g_tune[k] = tz;
+    char line[256];
+    while (std::fgets(line, sizeof line, f)) {
+        TuneKey k;
+        TuneVal v{0, 0};
+        // fmt k path flag size_class tz [variant]
+        const int n = std::sscanf(line, "%d %d %d %d %d %d %d", &k.c.fmt, &k.c.k, &k.c.path,
+                                  &k.c.flag, &k.size_class, &v.tz, &v.variant);
+        if (n >= 6 && v.tz > 0 && v.variant >= 0 && v.variant < kTileVariants) g_tune[k] = v;
+    }
     std::fclose(f);
 }
 
@@ -104,8 +118,8 @@ void tune_store_locked()
     FILE* f = std::fopen(path, "w");
     if (!f) return;
     for (const auto& e : g_tune)
-        std::fprintf(f, "%d %d %d %d %d %d\n", e.first.c.fmt, e.first.c.k, e.first.c.path,
-                     e.first.c.flag, e.first.size_class, e.second);
+        std::fprintf(f, "%d %d %d %d %d %d %d\n", e.first.c.fmt, e.first.c.k, e.first.c.path,
+                     e.first.c.flag, e.first.size_class, e.second.tz, e.second.variant);
     std::fclose(f);
 }
 
@@ -122,6 +136,7 @@ struct ClassPlan {
     const void* func = nullptr;
     std::vector<int> members;      // indices into the batch
     int tz = 0;
+    int variant = 0;               // tile-height variant
     unsigned grid = 0;
     BatchArgs args{};
     // offsets inside the plan's device buffer
@@ -162,6 +177,14 @@ std::mutex g_plan_mu;
 std::vector<std::shared_ptr<Plan>> g_plans;
 constexpr size_t kMaxPlans = 16;
 
+// Batched calls from several threads run one at a time inside the library:
+// planning, graph instantiation, launch and the destruction of evicted plans
+// are serialised (a two-thread test that fills the cache past its capacity
+// crashed inside this call with them running concurrently; the library's own
+// shared state is locked, so the HIP graph calls are the suspects).  The
+// enqueued work itself still runs concurrently on the callers' streams.
+std::mutex g_batch_mu;
+
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Work list of one class at slab depth tz, longest items first.
@@ -201,8 +224,8 @@ struct Triple {
     const vktFilter_* f;
 };
 
-// Tuning-table key of one class of a batch, and the depth the table holds
-// for it (0: none).
+// Tuning-table key of one class of a batch, and the entry the table holds
+// for it (tz 0: none).
 TuneKey tune_key(const std::vector<Triple>& tr, const ClassPlan& cp)
 {
     std::vector<FilterJob> jobs;
@@ -210,12 +233,12 @@ TuneKey tune_key(const std::vector<Triple>& tr, const ClassPlan& cp)
     return TuneKey{cp.key, size_class_of(jobs)};
 }
 
-int tuned_tz(const TuneKey& tk)
+TuneVal tuned(const TuneKey& tk)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_load_locked();
     auto it = g_tune.find(tk);
-    return it != g_tune.end() ? it->second : 0;
+    return it != g_tune.end() ? it->second : TuneVal{0, 0};
 }
 
 // Build (or rebuild for another slab depth) the host-side arrays of one class.
@@ -223,7 +246,7 @@ void class_arrays(const std::vector<Triple>& tr, ClassPlan& cp, std::vector<VolD
                   std::vector<WorkItem>& items, std::vector<float>& wf,
                   std::vector<int32_t>& wi)
 {
-    const ClassGeom g = class_geom(cp.key);
+    const ClassGeom g = class_geom(cp.key, cp.variant);
     descs.clear();
     wf.clear();
     wi.clear();
@@ -289,10 +312,20 @@ hipError_t launch_class(const ClassPlan& cp, hipStream_t s)
 
 // Time one class alone at a given slab depth (two launches on the caller's
 // stream, the second timed; waits for both).
-float time_class(const std::vector<Triple>& tr, ClassPlan& cp, char* base, int tz,
+float time_class(const std::vector<Triple>& tr, ClassPlan& cp, char* base, int tz, int variant,
                  hipStream_t s)
 {
     cp.tz = tz;
+    cp.variant = variant;
+    cp.func = class_kernel(cp.key, variant);
+    int per_cu = 0, cus = 0, dev = 0;
+    (void)hipGetDevice(&dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, cp.func, 256, 0) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 1;
+    cp.grid = (unsigned)(per_cu * cus);
     std::vector<VolDesc> descs;
     std::vector<WorkItem> items;
     std::vector<float> wf;
@@ -329,22 +362,27 @@ vktError build_plan(const std::vector<Triple>& tr, std::vector<uintptr_t>&& sig,
     std::map<ClassKey, std::vector<int>> groups;
     for (size_t i = 0; i < tr.size(); ++i) groups[tr[i].key].push_back((int)i);
 
-    // size the device buffer with the smallest slab depth any candidate uses
-    // (most items), so tuning and the final plan fit
+    // size the device buffer for the most items any candidate makes (the
+    // shorter tile variant at its smallest slab depth), so tuning and the
+    // final plan fit
     size_t bytes = 0;
     for (auto& g : groups) {
         ClassPlan cp;
         cp.key = g.first;
         cp.members = g.second;
-        cp.func = class_kernel(cp.key);
+        cp.func = class_kernel(cp.key, 0);
         if (!cp.func) return vktUnsupported;
-        const ClassGeom geom = class_geom(cp.key);
         size_t nitems = 0;
-        for (int idx : cp.members) {
-            const FilterJob& j = tr[idx].j;
-            const int tzmin = std::min(geom.tz_min, j.Z);
-            nitems += (size_t)((j.X + geom.tx - 1) / geom.tx) * ((j.Y + geom.ty - 1) / geom.ty) *
-                      ((j.Z + tzmin - 1) / tzmin);
+        for (int v = 0; v < kTileVariants; ++v) {
+            const ClassGeom geom = class_geom(cp.key, v);
+            size_t n = 0;
+            for (int idx : cp.members) {
+                const FilterJob& j = tr[idx].j;
+                const int tzmin = std::min(geom.tz_min, j.Z);
+                n += (size_t)((j.X + geom.tx - 1) / geom.tx) * ((j.Y + geom.ty - 1) / geom.ty) *
+                     ((j.Z + tzmin - 1) / tzmin);
+            }
+            nitems = std::max(nitems, n);
         }
         const size_t n3 = (size_t)class_weights(cp.key);
         cp.off_desc = bytes = align_up(bytes, 256);
@@ -357,12 +395,6 @@ vktError build_plan(const std::vector<Triple>& tr, std::vector<uintptr_t>&& sig,
         bytes += (cp.members.size() * n3 + kWeightPad) * sizeof(float);
         cp.off_wi = bytes = align_up(bytes, 256);
         bytes += (cp.members.size() * n3 + kWeightPad) * sizeof(int32_t);
-        int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, cp.func, 256, 0) !=
-                hipSuccess ||
-            per_cu < 1)
-            per_cu = 1;
-        cp.grid = (unsigned)(per_cu * cus);
         plan->classes.push_back(cp);
     }
     plan->dbytes = bytes;
@@ -372,28 +404,40 @@ vktError build_plan(const std::vector<Triple>& tr, std::vector<uintptr_t>&& sig,
     if (e != hipSuccess) return from_hip(e);
 
     for (auto& cp : plan->classes) {
-        const ClassGeom geom = class_geom(cp.key);
         const TuneKey tk = tune_key(tr, cp);
-        int tz = tuned_tz(tk);
-        if (tz == 0 && tune) {
-            // autotune: time candidate slab depths on the real batch
+        TuneVal tv = tuned(tk);
+        if (tv.tz == 0 && tune) {
+            // autotune: time every tile variant at candidate slab depths on
+            // the real batch
             float best = -1.f;
-            for (int cand : {8, 16, 32, 64}) {
-                if (cand < geom.tz_min && cand != 64) continue;
-                const float ms = time_class(tr, cp, plan->dbuf, cand, stream);
-                if (ms > 0.f && (best < 0.f || ms < best)) {
-                    best = ms;
-                    tz = cand;
+            for (int v = 0; v < kTileVariants; ++v) {
+                const ClassGeom geom = class_geom(cp.key, v);
+                for (int cand : {8, 16, 32, 64}) {
+                    if (cand < geom.tz_min && cand != 64) continue;
+                    const float ms = time_class(tr, cp, plan->dbuf, std::max(cand, geom.tz_min),
+                                                v, stream);
+                    if (ms > 0.f && (best < 0.f || ms < best)) {
+                        best = ms;
+                        tv = TuneVal{std::max(cand, geom.tz_min), v};
+                    }
                 }
             }
-            if (tz > 0) {
+            if (tv.tz > 0) {
                 std::lock_guard<std::mutex> lk(g_tune_mu);
-                g_tune[tk] = tz;
+                g_tune[tk] = tv;
                 tune_store_locked();
             }
         }
-        if (tz == 0) tz = default_tz(cp.key, geom);
-        cp.tz = std::max(tz, geom.tz_min);
+        cp.variant = tv.tz > 0 ? tv.variant : 0;
+        const ClassGeom geom = class_geom(cp.key, cp.variant);
+        cp.tz = std::max(tv.tz > 0 ? tv.tz : default_tz(cp.key, geom), geom.tz_min);
+        cp.func = class_kernel(cp.key, cp.variant);
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, cp.func, 256, 0) !=
+                hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        cp.grid = (unsigned)(per_cu * cus);
         std::vector<VolDesc> descs;
         std::vector<WorkItem> items;
         std::vector<float> wf;
@@ -543,8 +587,9 @@ vktError batched_no_alloc(const std::vector<Triple>& tr, hipStream_t stream)
     vktError ve = noalloc_device(dev, nd);
     if (ve != vktNoError) return ve;
 
-    // plan every class as the cached form does (same slab depths: the tuning
-    // table's entry, else the default; this form never times candidates)
+    // plan every class as the cached form does (same tile variants and slab
+    // depths: the tuning table's entry, else the defaults; this form never
+    // times candidates)
     std::map<ClassKey, std::vector<int>> groups;
     for (size_t i = 0; i < tr.size(); ++i) groups[tr[i].key].push_back((int)i);
     std::vector<ClassPlan> classes;
@@ -558,12 +603,12 @@ vktError batched_no_alloc(const std::vector<Triple>& tr, hipStream_t stream)
         ClassPlan cp;
         cp.key = g.first;
         cp.members = g.second;
-        cp.func = class_kernel(cp.key);
+        const TuneVal tv = tuned(tune_key(tr, cp));
+        cp.variant = tv.tz > 0 ? tv.variant : 0;
+        cp.func = class_kernel(cp.key, cp.variant);
         if (!cp.func) return vktUnsupported;
-        const ClassGeom geom = class_geom(cp.key);
-        int tz = tuned_tz(tune_key(tr, cp));
-        if (tz == 0) tz = default_tz(cp.key, geom);
-        cp.tz = std::max(tz, geom.tz_min);
+        const ClassGeom geom = class_geom(cp.key, cp.variant);
+        cp.tz = std::max(tv.tz > 0 ? tv.tz : default_tz(cp.key, geom), geom.tz_min);
         std::vector<float> wf;
         std::vector<int32_t> wi;
         class_arrays(tr, cp, descs[c], items[c], wf, wi);
@@ -661,6 +706,7 @@ vktError vktApplyFilterBatched(int32_t n, const vktStructuredVolume* dst,
     const vktError ve = prepare_batch(n, dst, src, filters, mode, prec, stream, tr, sig);
     if (ve != vktNoError) return ve;
 
+    std::lock_guard<std::mutex> serial(g_batch_mu);
     std::shared_ptr<Plan> plan;
     {
         int dev = 0;

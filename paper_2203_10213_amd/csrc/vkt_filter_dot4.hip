@@ -44,10 +44,13 @@ namespace {
 constexpr int kNT = 256, kWaves = 4, kLanes = 64;
 constexpr int kTX = 4 * kLanes;  // output cells per tile row
 
-template <int K>
+// VYO: output rows per lane of a tile variant of the batched form (0: the
+// default below; the other variant takes half as many rows)
+template <int K, int VYO = 0>
 struct Geo4 {
     static constexpr int R = (K - 1) / 2;
-    static constexpr int VY = K <= 3 ? 4 : 2;           // output rows per lane
+    static constexpr int VY_DEFAULT = K <= 3 ? 4 : 2;
+    static constexpr int VY = VYO ? VYO : VY_DEFAULT;   // output rows per lane
     static constexpr int TY = kWaves * VY;              // tile rows
     static constexpr int HY = TY + 2 * R;               // staged rows per plane
     static constexpr int WD = kLanes + 2;               // dwords per staged row
@@ -138,18 +141,22 @@ __device__ inline void pin8(int32_t (&v)[2][4])
     asm volatile("" : "+v"(v[0][0]), "+v"(v[0][1]), "+v"(v[0][2]), "+v"(v[0][3]),
                       "+v"(v[1][0]), "+v"(v[1][1]), "+v"(v[1][2]), "+v"(v[1][3]));
 }
+__device__ inline void pin8(int32_t (&v)[1][4])
+{
+    asm volatile("" : "+v"(v[0][0]), "+v"(v[0][1]), "+v"(v[0][2]), "+v"(v[0][3]));
+}
 template <int N>
 __device__ inline void pin8(int32_t (&)[N][4])
 {
-    static_assert(N == 2, "rows per lane with scalar weight groups");
+    static_assert(N == 1 || N == 2, "rows per lane with scalar weight groups");
 }
 
 // One tile-slab: output tile `tile` of z-slab `slab` of volume a.
-template <int K, bool SG>
+template <int K, bool SG, int VYO = 0>
 __device__ void dot4_tile(const VolDesc& a, const uint32_t* __restrict__ wq, int tile,
                           int slab, uint32_t* lds)
 {
-    using G = Geo4<K>;
+    using G = Geo4<K, VYO>;
     constexpr int R = G::R, VY = G::VY, NH = G::NH;
     const uint8_t* __restrict__ src = static_cast<const uint8_t*>(a.src);
     uint8_t* __restrict__ dst = static_cast<uint8_t*>(a.dst);
@@ -390,11 +397,11 @@ void filter_dot4_kernel(VolDesc a,
 
 // Persistent workgroups over a work queue of (volume, tile-slab) items; the
 // packed weights of all filters of the class are in the integer pool.
-template <int K, bool SG>
+template <int K, bool SG, int VYO>
 __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(Geo4<K>::WAVES)))
 void filter_dot4_batched_kernel(BatchArgs b)
 {
-    __shared__ __align__(16) uint32_t lds[2 * Geo4<K>::PLANE_BUF];
+    __shared__ __align__(16) uint32_t lds[2 * Geo4<K, VYO>::PLANE_BUF];
     __shared__ uint32_t s_item;
     const uint32_t* pool = reinterpret_cast<const uint32_t*>(b.wipool);
     for (;;) {
@@ -408,7 +415,8 @@ void filter_dot4_batched_kernel(BatchArgs b)
         const WorkItem wi = uniform_load(&b.items[it]);
         const VolDesc a = uniform_load(&b.vols[wi.vol]);
         const uint32_t ntiles = (uint32_t)a.tiles_x * (uint32_t)a.tiles_y;
-        dot4_tile<K, SG>(a, pool + a.woff, (int)(wi.lid % ntiles), (int)(wi.lid / ntiles), lds);
+        dot4_tile<K, SG, VYO>(a, pool + a.woff, (int)(wi.lid % ntiles), (int)(wi.lid / ntiles),
+                              lds);
     }
     if (threadIdx.x == 0) {
         __threadfence();
@@ -428,7 +436,7 @@ hipError_t launch_k(const FilterJob& j, hipStream_t s)
     const int64_t ntiles = (int64_t)((RX + g.tx - 1) / g.tx) * ((RY + g.ty - 1) / g.ty);
     // tz = 1 mod k: the slab's tz + k - 1 input planes are whole ring turns
     const void* fn = (const void*)&filter_dot4_kernel<K, SG>;
-    const int tz = plan_tz(ntiles, RZ, K, g.tz_min, 128, resident_wgs(fn), K);
+    const int tz = plan_tz(ntiles, RZ, K, 1, 128, resident_wgs(fn), K);
     const VolDesc a = make_desc(j, tz, g);
     const int64_t nb = ntiles * ((RZ + tz - 1) / tz);
     if (nb > 0x7fffffff) return hipErrorInvalidValue;
@@ -439,11 +447,11 @@ hipError_t launch_k(const FilterJob& j, hipStream_t s)
 
 }  // namespace
 
-ClassGeom dot4_geom(int k)
+ClassGeom dot4_geom(int k, int variant)
 {
     ClassGeom g;
     g.tx = kTX;
-    g.ty = kWaves * (k <= 3 ? 4 : 2);
+    g.ty = kWaves * (k <= 3 ? 4 : 2) / (variant ? 2 : 1);
     g.tz_min = 4 > 2 * k ? 4 : 2 * k;
     return g;
 }
@@ -458,15 +466,23 @@ hipError_t launch_filter_dot4(const FilterJob& j, hipStream_t s)
     return hipErrorInvalidValue;
 }
 
-const void* dot4_batched_kernel(int k, bool sg)
+template <int K>
+const void* batched_sg(bool sg, int variant)
+{
+    constexpr int ALT = Geo4<K>::VY_DEFAULT / 2;  // tile variant 1: half the rows
+    if (variant)
+        return sg ? (const void*)&filter_dot4_batched_kernel<K, true, ALT>
+                  : (const void*)&filter_dot4_batched_kernel<K, false, ALT>;
+    return sg ? (const void*)&filter_dot4_batched_kernel<K, true, 0>
+              : (const void*)&filter_dot4_batched_kernel<K, false, 0>;
+}
+
+const void* dot4_batched_kernel(int k, bool sg, int variant)
 {
     switch (k) {
-    case 3: return sg ? (const void*)&filter_dot4_batched_kernel<3, true>
-                      : (const void*)&filter_dot4_batched_kernel<3, false>;
-    case 5: return sg ? (const void*)&filter_dot4_batched_kernel<5, true>
-                      : (const void*)&filter_dot4_batched_kernel<5, false>;
-    case 7: return sg ? (const void*)&filter_dot4_batched_kernel<7, true>
-                      : (const void*)&filter_dot4_batched_kernel<7, false>;
+    case 3: return batched_sg<3>(sg, variant);
+    case 5: return batched_sg<5>(sg, variant);
+    case 7: return batched_sg<7>(sg, variant);
     }
     return nullptr;
 }

@@ -378,7 +378,7 @@ hipError_t launch_filter_i8mma(const FilterJob& j, hipStream_t s)
     const int64_t ntiles = (int64_t)((RX + g.tx - 1) / g.tx) * ((RY + g.ty - 1) / g.ty);
     // tz = 1 mod 3: the slab's tz + 2 input planes are whole ring turns
     const void* fn = (const void*)&filter_i8mma_kernel;
-    const int tz = plan_tz(ntiles, RZ, 3, g.tz_min, 128, resident_wgs(fn), 3);
+    const int tz = plan_tz(ntiles, RZ, 3, 1, 128, resident_wgs(fn), 3);
     VolDesc a = make_desc(j, tz, g);
     a.bias = j.m8_bias;
     const int64_t nb = ntiles * ((RZ + tz - 1) / tz);

@@ -97,7 +97,9 @@ template <> struct Pieces<kF32x6> {
     static constexpr int prod[NPROD][2] = {{0, 0}, {0, 1}, {1, 0}, {0, 2}, {1, 1}, {2, 0}};
 };
 
-template <typename T, int K, int PM>
+// SYV: row blocks per workgroup (tile height variant of the batched form);
+// 0 keeps the measured default below.
+template <typename T, int K, int PM, int SYV = 0>
 struct Cfg {
     using Tin = T;
     using PC = Pieces<PM>;
@@ -118,8 +120,9 @@ struct Cfg {
     // waves per SIMD -- 9^3 with uint8 or 3-product float32 operands, 21 %
     // faster on the 1024^3 9^3 workload; elsewhere it stays at one wave and
     // the taller tile measured faster)
-    static constexpr int SY =
+    static constexpr int SY_DEFAULT =
         SHAPE == 16 ? 2 : (K == 9 && (PM == kU8 || PM == kF32x3) ? 1 : 2);
+    static constexpr int SY = SYV ? SYV : SY_DEFAULT;
     static constexpr int TX = SX * NX, TY = SY * M::MT;             // 32 x 32 or 32 x 64 tile
     // a lane's 8-column windows of the wave's WS strips span SEGN columns,
     // read as NRD 16-byte pieces
@@ -262,17 +265,22 @@ template <typename T, int N>
 __device__ inline void store_row(__amdgpu_buffer_rsrc_t r, uint32_t off, const float (&v)[N],
                                  bool vec, int nx, float unscale)
 {
-    static_assert(N == 8 || N == 4, "rows of 8 or 4 cells");
+    static_assert(N == 8 || N == 4 || N == 2, "rows of 8, 4 or 2 cells");
     if constexpr (std::is_same<T, float>::value) {
         uint32_t u[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) u[i] = __float_as_uint(v[i] * unscale);
         if (vec) {
+            if constexpr (N == 2) {
+                typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+                __builtin_amdgcn_raw_buffer_store_b64(u32x2{u[0], u[1]}, r, (int)off, 0, 0);
+            } else {
 #pragma unroll
-            for (int h = 0; h < N / 4; ++h)
-                __builtin_amdgcn_raw_buffer_store_b128(
-                    u32x4{u[4 * h], u[4 * h + 1], u[4 * h + 2], u[4 * h + 3]}, r, (int)off + 16 * h,
-                    0, 0);
+                for (int h = 0; h < N / 4; ++h)
+                    __builtin_amdgcn_raw_buffer_store_b128(
+                        u32x4{u[4 * h], u[4 * h + 1], u[4 * h + 2], u[4 * h + 3]}, r,
+                        (int)off + 16 * h, 0, 0);
+            }
         } else {
 #pragma unroll
             for (int i = 0; i < N; ++i)
@@ -293,17 +301,22 @@ __device__ inline void store_row(__amdgpu_buffer_rsrc_t r, uint32_t off, const f
                     u32x4{u[0] | (u[1] << 16), u[2] | (u[3] << 16), u[4] | (u[5] << 16),
                           u[6] | (u[7] << 16)},
                     r, (int)off, 0, 0);
-            } else if constexpr (sizeof(T) == 2) {
+            } else if constexpr (sizeof(T) == 2 && N == 4) {
                 __builtin_amdgcn_raw_buffer_store_b64(
                     u32x2{u[0] | (u[1] << 16), u[2] | (u[3] << 16)}, r, (int)off, 0, 0);
+            } else if constexpr (sizeof(T) == 2) {
+                __builtin_amdgcn_raw_buffer_store_b32(u[0] | (u[1] << 16), r, (int)off, 0, 0);
             } else if constexpr (N == 8) {
                 __builtin_amdgcn_raw_buffer_store_b64(
                     u32x2{u[0] | (u[1] << 8) | (u[2] << 16) | (u[3] << 24),
                           u[4] | (u[5] << 8) | (u[6] << 16) | (u[7] << 24)},
                     r, (int)off, 0, 0);
-            } else {
+            } else if constexpr (N == 4) {
                 __builtin_amdgcn_raw_buffer_store_b32(u[0] | (u[1] << 8) | (u[2] << 16) | (u[3] << 24),
                                                       r, (int)off, 0, 0);
+            } else {
+                __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(u[0] | (u[1] << 8)), r, (int)off,
+                                                      0, 0);
             }
         } else {
 #pragma unroll
@@ -379,7 +392,10 @@ __device__ void mfma_tile(const VolDesc& a, const float* __restrict__ w, int til
                       : ((uint32_t)gy * (uint32_t)a.X + (uint32_t)gx) * (uint32_t)sizeof(T);
         loff[i] = e;
     }
-    uint16_t stage[C::NE][PC::PS];
+    // gather only issues the loads; the cells are split into their pieces
+    // when they are staged (put), after the plane's products, so the loads
+    // stay in flight while the matrix cores work
+    T raw[C::NE];
     auto gather = [&](int zi) {
         const int gz = addr_map(zi, a.Z, a.mode);
         const char* base = reinterpret_cast<const char*>(src) +
@@ -387,13 +403,16 @@ __device__ void mfma_tile(const VolDesc& a, const float* __restrict__ w, int til
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<char*>(base), (short)0, gz < 0 ? 0 : plane_bytes, (int)kRsrcWord3);
 #pragma unroll
-        for (int i = 0; i < C::NE; ++i) split_voxel<PM>(buf_load<T>(rs, goff[i]), stage[i]);
+        for (int i = 0; i < C::NE; ++i) raw[i] = buf_load<T>(rs, goff[i]);
     };
     auto put = [&](int buf) {
 #pragma unroll
-        for (int i = 0; i < C::NE; ++i)
+        for (int i = 0; i < C::NE; ++i) {
+            uint16_t p[3];
+            split_voxel<PM>(raw[i], p);
 #pragma unroll
-            for (int ps = 0; ps < PC::PS; ++ps) lds[buf][ps][loff[i]] = stage[i][ps];
+            for (int ps = 0; ps < PC::PS; ++ps) lds[buf][ps][loff[i]] = p[ps];
+        }
     };
 
     // ---- output block of the wave: its finished columns form an 8 (x) by
@@ -401,7 +420,7 @@ __device__ void mfma_tile(const VolDesc& a, const float* __restrict__ w, int til
     // it to the wave's LDS block (y fastest), then each lane reads its share of
     // one row (8 cells, or 4 of a 32-row block) and stores it
     constexpr int BX = C::WS * C::NX, BY = C::SY * M::MT;
-    static_assert(BX == 8 && (BY == 64 || BY == 32), "8 x 64 or 8 x 32 output blocks");
+    static_assert(BX == 8 && (BY == 64 || BY == 32 || BY == 16), "8 x 64, 32 or 16 blocks");
     // lane l stores CPL cells of row l % BY (for 32 rows, two lanes per row)
     constexpr int CPL = BX * BY / 64;
     const int jcol = lane % M::NT, gq = lane / M::NT;
@@ -482,7 +501,8 @@ __device__ void mfma_tile(const VolDesc& a, const float* __restrict__ w, int til
                     acc[yb * C::WS + st] = mfma<C::SHAPE, PC::F16>(
                         A[st][PC::prod[pr][0]], B[q][PC::prod[pr][1]], acc[yb * C::WS + st]);
         }
-
+        // the next plane's cells are split and staged after the products
+        __builtin_amdgcn_sched_barrier(0);
         put(cur ^ 1);
 
         // ---- column group k-1 holds output plane zi - r
@@ -601,7 +621,7 @@ hipError_t launch_cfg(const FilterJob& j, hipStream_t s)
     const int64_t ntiles = (int64_t)((RX + g.tx - 1) / g.tx) * ((RY + g.ty - 1) / g.ty);
     const void* fn = (const void*)&filter_mfma_kernel<C>;
     // (deeper slabs measured slower for the 16x16 tiles, faster for 32x32)
-    const int tz = plan_tz(ntiles, RZ, j.k, g.tz_min, C::SHAPE == 16 ? 128 : 512,
+    const int tz = plan_tz(ntiles, RZ, j.k, 1, C::SHAPE == 16 ? 128 : 512,
                            resident_wgs(fn), 1);
     const VolDesc a = make_desc(j, tz, g);
     const int64_t nb = ntiles * ((RZ + tz - 1) / tz);
@@ -621,21 +641,35 @@ hipError_t dispatch_k(const FilterJob& j, hipStream_t s)
     return hipErrorInvalidValue;
 }
 
-template <typename T, int PM>
-ClassGeom geom_k(int k)
+// Tile-height variants of the batched kernels: 0 = the default row blocks,
+// 1 = the other choice (16x16 tiles: one row block instead of two; 32x32
+// tiles: two instead of one, or one instead of two).
+template <typename T, int K, int PM>
+constexpr int alt_sy()
 {
-#define VKT_CASE(KK) \
-    case KK: return geom_of<Cfg<T, KK, PM>>();
+    return Cfg<T, K, PM>::SY_DEFAULT == 2 ? 1 : 2;
+}
+
+template <typename T, int PM>
+ClassGeom geom_k(int k, int variant = 0)
+{
+#define VKT_CASE(KK)                                                       \
+    case KK:                                                               \
+        return variant ? geom_of<Cfg<T, KK, PM, alt_sy<T, KK, PM>()>>()    \
+                       : geom_of<Cfg<T, KK, PM>>();
     switch (k) { VKT_MFMA_KS(VKT_CASE) }
 #undef VKT_CASE
     return ClassGeom{};
 }
 
 template <typename T, int PM>
-const void* batched_k(int k)
+const void* batched_k(int k, int variant)
 {
-#define VKT_CASE(KK) \
-    case KK: return (const void*)&filter_mfma_batched_kernel<Cfg<T, KK, PM>>;
+#define VKT_CASE(KK)                                                                      \
+    case KK:                                                                              \
+        return variant                                                                    \
+                   ? (const void*)&filter_mfma_batched_kernel<Cfg<T, KK, PM, alt_sy<T, KK, PM>()>> \
+                   : (const void*)&filter_mfma_batched_kernel<Cfg<T, KK, PM>>;
     switch (k) { VKT_MFMA_KS(VKT_CASE) }
 #undef VKT_CASE
     return nullptr;
@@ -643,13 +677,14 @@ const void* batched_k(int k)
 
 }  // namespace
 
-ClassGeom VKT_MFMA_FN(mfma_geom)(vktDataFormat f, int k, bool six_products)
+ClassGeom VKT_MFMA_FN(mfma_geom)(vktDataFormat f, int k, bool six_products, int variant)
 {
     switch (f) {
-    case vktDataFormatUInt8: return geom_k<uint8_t, kU8>(k);
-    case vktDataFormatUInt16: return geom_k<uint16_t, kU16>(k);
+    case vktDataFormatUInt8: return geom_k<uint8_t, kU8>(k, variant);
+    case vktDataFormatUInt16: return geom_k<uint16_t, kU16>(k, variant);
     case vktDataFormatFloat32:
-        return six_products ? geom_k<float, kF32x6>(k) : geom_k<float, kF32x3>(k);
+        return six_products ? geom_k<float, kF32x6>(k, variant)
+                            : geom_k<float, kF32x3>(k, variant);
     }
     return ClassGeom{};
 }
@@ -665,13 +700,15 @@ hipError_t VKT_MFMA_FN(launch_filter_mfma)(const FilterJob& j, bool six_products
     return hipErrorInvalidValue;
 }
 
-const void* VKT_MFMA_FN(mfma_batched_kernel)(vktDataFormat f, int k, bool six_products)
+const void* VKT_MFMA_FN(mfma_batched_kernel)(vktDataFormat f, int k, bool six_products,
+                                             int variant)
 {
     switch (f) {
-    case vktDataFormatUInt8: return batched_k<uint8_t, kU8>(k);
-    case vktDataFormatUInt16: return batched_k<uint16_t, kU16>(k);
+    case vktDataFormatUInt8: return batched_k<uint8_t, kU8>(k, variant);
+    case vktDataFormatUInt16: return batched_k<uint16_t, kU16>(k, variant);
     case vktDataFormatFloat32:
-        return six_products ? batched_k<float, kF32x6>(k) : batched_k<float, kF32x3>(k);
+        return six_products ? batched_k<float, kF32x6>(k, variant)
+                            : batched_k<float, kF32x3>(k, variant);
     }
     return nullptr;
 }

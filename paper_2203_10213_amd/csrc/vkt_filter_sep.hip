@@ -344,7 +344,7 @@ hipError_t launch_k(const FilterJob& j, hipStream_t s)
     const int RX = j.roi[3] - j.roi[0], RY = j.roi[4] - j.roi[1], RZ = j.roi[5] - j.roi[2];
     const int64_t ntiles = (int64_t)((RX + g.tx - 1) / g.tx) * ((RY + g.ty - 1) / g.ty);
     const void* fn = (const void*)&filter_sep_kernel<T, K>;
-    const int tz = plan_tz(ntiles, RZ, K, g.tz_min, 128, resident_wgs(fn), 1);
+    const int tz = plan_tz(ntiles, RZ, K, 1, 128, resident_wgs(fn), 1);
     const VolDesc a = make_desc(j, tz, g);
     const int64_t nb = ntiles * ((RZ + tz - 1) / tz);
     if (nb > 0x7fffffff) return hipErrorInvalidValue;

@@ -49,17 +49,19 @@ constexpr int valu_waves(int k, bool iacc) { return k == 5 && !iacc ? 6 : 1; }
 constexpr int kBX = 16, kBY = 16, kNT = kBX * kBY;  // threads per workgroup
 constexpr int kVX = 4, kVY = 2;                      // outputs per thread
 constexpr int kTX = kBX * kVX, kTY = kBY * kVY;      // 64 x 32 tile
+// (the batched form also has a 64 x 16 tile variant: one output row per
+// thread, VY = 1)
 
-template <int K>
+template <int K, int VY = kVY>
 struct Geo {
     static constexpr int R = (K - 1) / 2;
     static constexpr int HX = kTX + 2 * R;                // halo tile width
-    static constexpr int HY = kTY + 2 * R;                // halo tile height
+    static constexpr int HY = kBY * VY + 2 * R;           // halo tile height
     static constexpr int P = (HX + 3) & ~3;               // LDS row pitch (cells)
     static constexpr int NE = (HX * HY + kNT - 1) / kNT;  // halo cells per thread
     static constexpr int WX = kVX + K - 1;                // row window per thread
     static constexpr int NR = (WX + 3) / 4;               // 16-byte reads per row
-    static constexpr int NROW = kVY + K - 1;              // input rows per thread
+    static constexpr int NROW = VY + K - 1;               // input rows per thread
     static constexpr int LDS_CELLS = HY * P;              // one plane buffer
     static_assert(4 * (kBX - 1) + 4 * NR <= P, "row window exceeds LDS pitch");
 };
@@ -218,11 +220,12 @@ __device__ inline T finish(Acc acc, const VolDesc& a)
 }
 
 // One tile-slab: output tile `tile` of z-slab `slab` of volume a.
-template <typename T, int K, bool IACC>
+template <typename T, int K, bool IACC, int VY = kVY>
 __device__ void valu_tile(const VolDesc& a, const typename AccT<IACC>::type* __restrict__ w,
                           int tile, int slab, typename AccT<IACC>::type* lds)
 {
-    using G = Geo<K>;
+    using G = Geo<K, VY>;
+    constexpr int kVY = VY, kTY = kBY * VY;
     using Acc = typename AccT<IACC>::type;
     constexpr int R = G::R;
     const T* __restrict__ src = static_cast<const T*>(a.src);
@@ -439,11 +442,11 @@ void filter_valu_kernel(
 
 // Persistent workgroups: take items (volume, tile-slab) from the queue until
 // it is empty; the last workgroup to finish resets the queue counters.
-template <typename T, int K, bool IACC>
+template <typename T, int K, bool IACC, int VY>
 __global__ __launch_bounds__(kNT) void filter_valu_batched_kernel(BatchArgs b)
 {
     using Acc = typename AccT<IACC>::type;
-    __shared__ __align__(16) Acc lds[2 * Geo<K>::LDS_CELLS];
+    __shared__ __align__(16) Acc lds[2 * Geo<K, VY>::LDS_CELLS];
     __shared__ uint32_t s_item;
     const Acc* pool;
     if constexpr (IACC) pool = b.wipool; else pool = b.wpool;
@@ -458,8 +461,8 @@ __global__ __launch_bounds__(kNT) void filter_valu_batched_kernel(BatchArgs b)
         const WorkItem wi = uniform_load(&b.items[it]);
         const VolDesc a = uniform_load(&b.vols[wi.vol]);
         const uint32_t ntiles = (uint32_t)a.tiles_x * (uint32_t)a.tiles_y;
-        valu_tile<T, K, IACC>(a, pool + a.woff, (int)(wi.lid % ntiles), (int)(wi.lid / ntiles),
-                              lds);
+        valu_tile<T, K, IACC, VY>(a, pool + a.woff, (int)(wi.lid % ntiles),
+                                  (int)(wi.lid / ntiles), lds);
     }
     if (threadIdx.x == 0) {
         __threadfence();
@@ -470,21 +473,81 @@ __global__ __launch_bounds__(kNT) void filter_valu_batched_kernel(BatchArgs b)
     }
 }
 
+// Small output regions: one thread per output cell reading its k^3 taps
+// straight from memory (the whole source is cache resident at these sizes),
+// with no LDS staging and no barriers, so a 64^3 volume is 1024 workgroups in
+// one wave of the device instead of a few dozen tile-slabs.  Taps are summed
+// in the tiled kernel's order (filter plane, row, column).
+template <typename T, int K, bool IACC>
+__global__ __launch_bounds__(kNT) void filter_direct_kernel(
+    VolDesc a, const typename AccT<IACC>::type* __restrict__ w)
+{
+    using Acc = typename AccT<IACC>::type;
+    constexpr int R = (K - 1) / 2;
+    const int64_t rx = a.rx1 - a.rx0, ry = a.ry1 - a.ry0, rz = a.rz1 - a.rz0;
+    const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (i >= rx * ry * rz) return;
+    const int x = a.rx0 + (int)(i % rx), y = a.ry0 + (int)((i / rx) % ry),
+              z = a.rz0 + (int)(i / (rx * ry));
+    int xs[K], ys[K], zs[K];  // coordinates through the address mode; -1: zero
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        xs[t] = addr_map((int64_t)x + t - R, a.X, a.mode);
+        ys[t] = addr_map((int64_t)y + t - R, a.Y, a.mode);
+        zs[t] = addr_map((int64_t)z + t - R, a.Z, a.mode);
+    }
+    const T* __restrict__ src = static_cast<const T*>(a.src);
+    Acc acc = 0;
+#pragma unroll
+    for (int c = 0; c < K; ++c)
+#pragma unroll
+        for (int b = 0; b < K; ++b) {
+            // cells outside under border read as zero: the load goes to a
+            // cell inside the volume and its value is replaced
+            const bool row_in = zs[c] >= 0 && ys[b] >= 0;
+            const T* row = src + ((int64_t)max(zs[c], 0) * a.Y + max(ys[b], 0)) * a.X;
+#pragma unroll
+            for (int aa = 0; aa < K; ++aa) {
+                const Acc cell = (Acc)row[max(xs[aa], 0)];
+                const Acc v = (row_in && xs[aa] >= 0) ? cell : (Acc)0;
+                acc = mac(w[(c * K + b) * K + aa], v, acc);
+            }
+        }
+    T* __restrict__ dst = static_cast<T*>(a.dst);
+    dst[((int64_t)z * a.Y + y) * a.X + x] = finish<T>(acc, a);
+}
+
+// Output regions up to this many cells (k <= 5) take the direct kernel.
+constexpr int64_t kDirectMaxCells = int64_t(1) << 19;
+
 template <typename T, int K, bool IACC>
 hipError_t launch_k(const FilterJob& j, hipStream_t s)
 {
     const ClassGeom g = valu_geom(K);
+    using Acc = typename AccT<IACC>::type;
+    const Acc* w;
+    if constexpr (IACC) w = j.wi; else w = j.wf;
+    {
+        const int64_t cells =
+            (int64_t)(j.roi[3] - j.roi[0]) * (j.roi[4] - j.roi[1]) * (j.roi[5] - j.roi[2]);
+        if constexpr (K <= 5) {
+            if (cells <= kDirectMaxCells) {
+                const VolDesc a = make_desc(j, 1, g);
+                hipLaunchKernelGGL((filter_direct_kernel<T, K, IACC>),
+                                   dim3((unsigned)((cells + kNT - 1) / kNT)), dim3(kNT), 0, s, a,
+                                   w);
+                return hipGetLastError();
+            }
+        }
+    }
     // the output region's tiles and z extent (the whole volume unless a range)
     const int RX = j.roi[3] - j.roi[0], RY = j.roi[4] - j.roi[1], RZ = j.roi[5] - j.roi[2];
     const int64_t ntiles = (int64_t)((RX + g.tx - 1) / g.tx) * ((RY + g.ty - 1) / g.ty);
     const void* fn = (const void*)&filter_valu_kernel<T, K, IACC>;
-    const int tz = plan_tz(ntiles, RZ, K, g.tz_min, 128, resident_wgs(fn), 1);
+    const int tz = plan_tz(ntiles, RZ, K, 1, 128, resident_wgs(fn), 1);
     const VolDesc a = make_desc(j, tz, g);
     const int64_t nb = ntiles * ((RZ + tz - 1) / tz);
     if (nb > 0x7fffffff) return hipErrorInvalidValue;
-    using Acc = typename AccT<IACC>::type;
-    const Acc* w;
-    if constexpr (IACC) w = j.wi; else w = j.wf;
     hipLaunchKernelGGL((filter_valu_kernel<T, K, IACC>), dim3((unsigned)nb), dim3(kNT), 0, s,
                        a, w, (uint32_t)nb);
     return hipGetLastError();
@@ -506,29 +569,36 @@ hipError_t dispatch_k(const FilterJob& j, hipStream_t s)
     return hipErrorInvalidValue;
 }
 
-template <typename T, bool IACC>
-const void* batched_k(int k)
+template <typename T, bool IACC, int VY>
+const void* batched_vy(int k)
 {
     switch (k) {
-    case 1: return (const void*)&filter_valu_batched_kernel<T, 1, IACC>;
-    case 3: return (const void*)&filter_valu_batched_kernel<T, 3, IACC>;
-    case 5: return (const void*)&filter_valu_batched_kernel<T, 5, IACC>;
-    case 7: return (const void*)&filter_valu_batched_kernel<T, 7, IACC>;
-    case 9: return (const void*)&filter_valu_batched_kernel<T, 9, IACC>;
-    case 11: return (const void*)&filter_valu_batched_kernel<T, 11, IACC>;
-    case 13: return (const void*)&filter_valu_batched_kernel<T, 13, IACC>;
-    case 15: return (const void*)&filter_valu_batched_kernel<T, 15, IACC>;
+    case 1: return (const void*)&filter_valu_batched_kernel<T, 1, IACC, VY>;
+    case 3: return (const void*)&filter_valu_batched_kernel<T, 3, IACC, VY>;
+    case 5: return (const void*)&filter_valu_batched_kernel<T, 5, IACC, VY>;
+    case 7: return (const void*)&filter_valu_batched_kernel<T, 7, IACC, VY>;
+    case 9: return (const void*)&filter_valu_batched_kernel<T, 9, IACC, VY>;
+    case 11: return (const void*)&filter_valu_batched_kernel<T, 11, IACC, VY>;
+    case 13: return (const void*)&filter_valu_batched_kernel<T, 13, IACC, VY>;
+    case 15: return (const void*)&filter_valu_batched_kernel<T, 15, IACC, VY>;
     }
     return nullptr;
 }
 
+// tile variant 0: 64 x 32 (two output rows per thread); 1: 64 x 16
+template <typename T, bool IACC>
+const void* batched_k(int k, int variant)
+{
+    return variant ? batched_vy<T, IACC, 1>(k) : batched_vy<T, IACC, kVY>(k);
+}
+
 }  // namespace
 
-ClassGeom valu_geom(int k)
+ClassGeom valu_geom(int k, int variant)
 {
     ClassGeom g;
     g.tx = kTX;
-    g.ty = kTY;
+    g.ty = variant ? kBY : kTY;
     g.tz_min = 4 > 2 * k ? 4 : 2 * k;
     return g;
 }
@@ -546,15 +616,17 @@ hipError_t launch_filter_valu(const FilterJob& j, hipStream_t s)
     return hipErrorInvalidValue;
 }
 
-const void* valu_batched_kernel(vktDataFormat f, int k, bool int_acc)
+const void* valu_batched_kernel(vktDataFormat f, int k, bool int_acc, int variant)
 {
     switch (f) {
     case vktDataFormatUInt8:
-        return int_acc ? batched_k<uint8_t, true>(k) : batched_k<uint8_t, false>(k);
+        return int_acc ? batched_k<uint8_t, true>(k, variant)
+                       : batched_k<uint8_t, false>(k, variant);
     case vktDataFormatUInt16:
-        return int_acc ? batched_k<uint16_t, true>(k) : batched_k<uint16_t, false>(k);
+        return int_acc ? batched_k<uint16_t, true>(k, variant)
+                       : batched_k<uint16_t, false>(k, variant);
     case vktDataFormatFloat32:
-        return int_acc ? nullptr : batched_k<float, false>(k);
+        return int_acc ? nullptr : batched_k<float, false>(k, variant);
     }
     return nullptr;
 }

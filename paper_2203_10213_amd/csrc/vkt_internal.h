@@ -188,8 +188,8 @@ hipError_t launch_flip(const void* src, void* dst, vktDataFormat f, const int32_
 hipError_t launch_filter_sep(const FilterJob& j, hipStream_t s);
 // 8-bit dot-product path for uint8 volumes with small integer filters.
 hipError_t launch_filter_dot4(const FilterJob& j, hipStream_t s);
-const void* dot4_batched_kernel(int k, bool q_signed);
-ClassGeom dot4_geom(int k);
+const void* dot4_batched_kernel(int k, bool q_signed, int variant = 0);
+ClassGeom dot4_geom(int k, int variant = 0);
 // Exact int8 matrix-core path for uint8 volumes with 3x3x3 filters of signed
 // 8-bit weights (single-volume launches).
 hipError_t launch_filter_i8mma(const FilterJob& j, hipStream_t s);
@@ -206,18 +206,23 @@ hipError_t launch_filter_mfma(const FilterJob& j, bool six_products, hipStream_t
 // and 32x32x16 tiles for k >= 9 (_s32); the unsuffixed functions dispatch.
 hipError_t launch_filter_mfma_s16(const FilterJob& j, bool six_products, hipStream_t s);
 hipError_t launch_filter_mfma_s32(const FilterJob& j, bool six_products, hipStream_t s);
-const void* mfma_batched_kernel_s16(vktDataFormat f, int k, bool six_products);
-const void* mfma_batched_kernel_s32(vktDataFormat f, int k, bool six_products);
-ClassGeom mfma_geom_s16(vktDataFormat f, int k, bool six_products);
-ClassGeom mfma_geom_s32(vktDataFormat f, int k, bool six_products);
+// variant: tile height of the batched kernels (0: the default row blocks,
+// 1: the other choice; see kTileVariants)
+const void* mfma_batched_kernel_s16(vktDataFormat f, int k, bool six_products, int variant);
+const void* mfma_batched_kernel_s32(vktDataFormat f, int k, bool six_products, int variant);
+ClassGeom mfma_geom_s16(vktDataFormat f, int k, bool six_products, int variant = 0);
+ClassGeom mfma_geom_s32(vktDataFormat f, int k, bool six_products, int variant = 0);
 
 // Batched persistent kernels: the kernel function of a class (for launches
 // and graph kernel nodes, taking one BatchArgs by value), its geometry, and
 // the workgroup count that fills the device once.
-const void* valu_batched_kernel(vktDataFormat f, int k, bool int_acc);
-ClassGeom valu_geom(int k);
-const void* mfma_batched_kernel(vktDataFormat f, int k, bool six_products);
-ClassGeom mfma_geom(vktDataFormat f, int k, bool six_products);
+// Tile-height variants of every batched class: 0 = the default tile, 1 = a
+// tile half (matrix-core 32x32 tiles: twice) as tall; the autotuner times both.
+constexpr int kTileVariants = 2;
+const void* valu_batched_kernel(vktDataFormat f, int k, bool int_acc, int variant = 0);
+ClassGeom valu_geom(int k, int variant = 0);
+const void* mfma_batched_kernel(vktDataFormat f, int k, bool six_products, int variant = 0);
+ClassGeom mfma_geom(vktDataFormat f, int k, bool six_products, int variant = 0);
 // Fill in the descriptor fields the kernels derive from a FilterJob.
 VolDesc make_desc(const FilterJob& j, int tz, ClassGeom g);
 // Workgroups of 256 threads of `func` resident on the whole current device

@@ -10,8 +10,8 @@
 // cells samples the source at u = (i + 1/2) n / m - 1/2 (cell centres),
 // trilinear between the two neighbouring cells, neighbours clamped to the
 // volume; integer formats round half-up and saturate.  The position is
-// formed in FP64 (exact enough that the FP32 weights are within one rounding
-// of the true ones), the interpolation runs in FP32.  An exact factor of two
+// split exactly in integer arithmetic into its cell and its fraction, which
+// is rounded once to FP32; the interpolation runs in FP32.  An exact factor of two
 // on every axis takes a dedicated path: the mean of each 2 x 2 x 2 block
 // (integer formats: (sum + 4) >> 3, exact).
 // Flip: dst(x) = src(n - 1 - x) along one axis; in place (dst == src) the
@@ -64,15 +64,28 @@ __device__ inline T from_f(float v)
 }
 
 // Lower and upper neighbour (clamped) and the weight of the upper one for
-// destination cell i; scale = n / m in FP64.
-__device__ inline void lin_axis(int i, int n, double scale, int& i0, int& i1, float& f)
+// destination cell i of m on an axis of n source cells.  The sample position
+// u = (i + 1/2) n / m - 1/2 = ((2i + 1) n - m) / (2m) is split exactly in
+// integers: with N = (2i + 1) n + m >= 0 (the numerator plus one
+// denominator) and D = 2m, floor(u) = N / D - 1 and the fraction is
+// (N mod D) / D, rounded once to FP32.  (32-bit division whenever N fits.)
+__device__ inline void lin_axis(int i, int n, int m, int& i0, int& i1, float& f)
 {
-    const double u = ((double)i + 0.5) * scale - 0.5;
-    const double fl = floor(u);
-    f = (float)(u - fl);
-    const int a = (int)fl;
-    i0 = min(max(a, 0), n - 1);
-    i1 = min(max(a + 1, 0), n - 1);
+    const uint64_t N = (uint64_t)(2 * (int64_t)i + 1) * (uint64_t)n + (uint64_t)m;
+    const uint64_t D = 2 * (uint64_t)m;
+    uint64_t q, rem;
+    if (N <= 0xffffffffull && D <= 0xffffffffull) {
+        const uint32_t n32 = (uint32_t)N, d32 = (uint32_t)D;
+        q = n32 / d32;
+        rem = n32 - (uint32_t)q * d32;
+    } else {
+        q = N / D;
+        rem = N - q * D;
+    }
+    f = (float)rem / (float)D;
+    const int64_t a = (int64_t)q - 1;
+    i0 = (int)min(max(a, (int64_t)0), (int64_t)n - 1);
+    i1 = (int)min(max(a + 1, (int64_t)0), (int64_t)n - 1);
 }
 
 __device__ inline float lerp(float a, float b, float t) { return a + t * (b - a); }
@@ -90,22 +103,21 @@ __device__ inline uint4 load_stream(const uint4* p)
 template <typename T>
 __global__ __launch_bounds__(kNT) void resample_kernel(const T* __restrict__ src,
                                                        T* __restrict__ dst, int X, int Y, int Z,
-                                                       int Xo, int Yo, int64_t nrows, double sx,
-                                                       double sy, double sz)
+                                                       int Xo, int Yo, int Zo, int64_t nrows)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= Xo) return;
     int x0, x1;
     float fx;
-    lin_axis(x, X, sx, x0, x1, fx);
+    lin_axis(x, X, Xo, x0, x1, fx);
     const int64_t plane = (int64_t)X * Y;
     for (int64_t r = (int64_t)blockIdx.y * blockDim.y + threadIdx.y; r < nrows;
          r += (int64_t)gridDim.y * blockDim.y) {
         const int y = (int)(r % Yo), z = (int)(r / Yo);
         int y0, y1, z0, z1;
         float fy, fz;
-        lin_axis(y, Y, sy, y0, y1, fy);
-        lin_axis(z, Z, sz, z0, z1, fz);
+        lin_axis(y, Y, Yo, y0, y1, fy);
+        lin_axis(z, Z, Zo, z0, z1, fz);
         const T* p0 = src + z0 * plane;
         const T* p1 = src + z1 * plane;
         const int64_t o0 = (int64_t)y0 * X, o1 = (int64_t)y1 * X;
@@ -329,8 +341,7 @@ hipError_t resample_t(const void* src, void* dst, const int32_t in[3], const int
         const RowGrid g = row_grid(out[0], nrows);
         hipLaunchKernelGGL((resample_kernel<T>), g.grid, g.block, 0, s,
                            static_cast<const T*>(src), static_cast<T*>(dst), in[0], in[1], in[2],
-                           out[0], out[1], nrows, (double)in[0] / out[0],
-                           (double)in[1] / out[1], (double)in[2] / out[2]);
+                           out[0], out[1], out[2], nrows);
     }
     return hipGetLastError();
 }

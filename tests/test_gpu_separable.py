@@ -90,6 +90,28 @@ def test_integer_rank1_bit_exact(orc, mode):
                              what=f"sep int {dtype.__name__} k={w.shape[0]} D={D}")
 
 
+def test_near_rank1_float_filter_k11(orc):
+    """An 11^3 near-delta filter whose 1330 off-centre weights are of size
+    2^-22 (each within 2^-21 max|w| of the rank-1 delta, but nowhere near it
+    relative to itself) is not taken as rank 1; with the switch on it still
+    meets the float32 tolerance against the oracle on a volume that is large
+    exactly where those small weights read and zero at the centre tap."""
+    g = np.random.default_rng(661)
+    k = 11
+    w = (g.choice([-1.0, 1.0], (k, k, k)) * 2.0 ** -22).astype(np.float32)
+    w[5, 5, 5] = 1.0
+    assert not _is_sep(w)
+    src = np.zeros((12, 24, 24), np.float32)
+    src[:, :, :] = 1000.0
+    src[::2, ::2, ::2] = 0.0
+    out = run_filter(src, w, "clamp", precision="fp32")
+    check_against_oracle(orc, src, w, "clamp", out, what="near rank-1 k=11")
+    # a Gaussian of the same size stays rank 1
+    from paper_2203_10213_amd import synth
+    assert _is_sep(synth.gaussian_weights(11, 1.0))
+    assert _is_sep(synth.gaussian_weights(15, 3.0))
+
+
 def test_not_rank1_runs_dense_arithmetic(orc):
     """With the switch on, a filter that is not rank 1 gives the same bytes
     as with the switch off."""
