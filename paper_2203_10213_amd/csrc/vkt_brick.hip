@@ -120,6 +120,99 @@ __global__ __launch_bounds__(kNT) void brick_kernel(BrickArgs a)
     }
 }
 
+// uint8 bricks whose rows are whole dwords (row length, source row length and
+// buffers multiples of 4 bytes): each thread writes whole destination dwords.
+// A dword inside the source row is formed from the two aligned source dwords
+// it straddles and one byte align (v_alignbyte); dwords that reach past an x
+// face of the volume take their four cells through the address mode.  The
+// row offsets of the workgroup's 64 rows are resolved once, into LDS.
+__global__ __launch_bounds__(kNT) void brick_u8_dword_kernel(BrickArgs a)
+{
+    __shared__ int64_t s_row[kRowsPerWG];
+    const uint32_t logical = xcd_group(blockIdx.x, gridDim.x);
+    const int bl = (int)(logical % (uint32_t)a.count);
+    const int chunk = (int)(logical / (uint32_t)a.count);
+    const int b = a.first + bl;
+    const int bx = b % a.nbx, by = (b / a.nbx) % a.nby, bz = b / (a.nbx * a.nby);
+    const int o[3] = {bx * a.B[0] - a.G[0], by * a.B[1] - a.G[1], bz * a.B[2] - a.G[2]};
+    const int dx = min(a.B[0], a.X - bx * a.B[0]) + 2 * a.G[0];
+    const int dy = min(a.B[1], a.Y - by * a.B[1]) + 2 * a.G[1];
+    const int dz = min(a.B[2], a.Z - bz * a.B[2]) + 2 * a.G[2];
+    const int64_t nrows = (int64_t)dy * dz;
+    const int64_t r0 = (int64_t)chunk * kRowsPerWG;
+    if (r0 >= nrows) return;  // the whole workgroup (before any barrier)
+    const int rows = (int)min((int64_t)kRowsPerWG, nrows - r0);
+    const int t = threadIdx.x + 64 * threadIdx.y;
+    if (t < rows) {
+        const int64_t r = r0 + t;
+        const int z = (int)(r / dy), y = (int)(r - (int64_t)z * dy);
+        const int sy = brick_addr((int64_t)o[1] + y, a.Y, a.mode);
+        const int sz = brick_addr((int64_t)o[2] + z, a.Z, a.mode);
+        s_row[t] = (sy | sz) >= 0 ? ((int64_t)sz * a.Y + sy) * a.X : -1;
+    }
+    __syncthreads();
+    const uint8_t* __restrict__ src = static_cast<const uint8_t*>(a.src);
+    uint32_t* __restrict__ dst = static_cast<uint32_t*>(a.dst[bl]) + r0 * (dx / 4);
+    const int nd = dx / 4;
+    // Dword j of a row covers source x in [o[0] + 4 j, o[0] + 4 j + 4); it
+    // lies inside the source row for j in [jlo, jhi), the same for every row
+    // of the brick.
+    const int jlo = o[0] >= 0 ? 0 : min(nd, (3 - o[0]) / 4);
+    const int last = a.X - 4 - o[0];  // largest 4 j inside the row
+    const int jhi = max(jlo, last >= 0 ? min(nd, last / 4 + 1) : 0);
+    const int ni = jhi - jlo, nf = nd - ni;
+    // Interior dwords, in batches of kBatch per thread: all loads of a batch
+    // are issued before its stores.  A dword at byte offset p is the aligned
+    // pair (lo, hi) around it shifted by p & 3 bytes (v_alignbyte; shift 0
+    // gives lo).  Rows outside the volume under border read as zero.
+    constexpr int kBatch = 8;
+    const int n = rows * ni;
+    for (int i0 = t; i0 < n; i0 += kBatch * kNT) {
+        uint32_t lo[kBatch], hi[kBatch], sh[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int i = i0 + u * kNT;
+            lo[u] = hi[u] = sh[u] = 0;
+            const int rl = i < n ? i / ni : 0;
+            const int64_t so = s_row[rl];
+            if (i < n && so >= 0) {
+                const int64_t p = so + o[0] + 4 * (jlo + (i - rl * ni));
+                const uint32_t* q = reinterpret_cast<const uint32_t*>(src + (p & ~int64_t(3)));
+                sh[u] = (uint32_t)(p & 3);
+                lo[u] = q[0];
+                // the next aligned dword is inside the row when p is not
+                // aligned (rows end on a dword boundary)
+                if (sh[u]) hi[u] = q[1];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int i = i0 + u * kNT;
+            if (i < n) {
+                const int rl = i / ni;
+                dst[(int64_t)rl * nd + jlo + (i - rl * ni)] =
+                    __builtin_amdgcn_alignbyte(hi[u], lo[u], sh[u]);
+            }
+        }
+    }
+    // Dwords that reach past an x face: four cells through the address mode.
+    const int m = rows * nf;
+    for (int i = t; i < m; i += kNT) {
+        const int rl = i / nf, jf = i - rl * nf;
+        const int j = jf < jlo ? jf : jhi + (jf - jlo);
+        const int64_t so = s_row[rl];
+        const int sx = o[0] + 4 * j;
+        uint32_t v = 0;
+        if (so >= 0) {
+            for (int c = 0; c < 4; ++c) {
+                const int cx = brick_addr((int64_t)sx + c, a.X, a.mode);
+                if (cx >= 0) v |= (uint32_t)src[so + cx] << (8 * c);
+            }
+        }
+        dst[(int64_t)rl * nd + j] = v;
+    }
+}
+
 int bricks_along(int32_t dim, int32_t b) { return (dim + b - 1) / b; }
 
 // Dims of brick (bx, by, bz) of src with ghosts.
@@ -148,13 +241,27 @@ hipError_t launch_bricks(BrickArgs& a, const std::vector<void*>& dsts, hipStream
     const int64_t chunks = (rows_max + kRowsPerWG - 1) / kRowsPerWG;
     if (chunks * kMaxBricks > INT32_MAX) return hipErrorInvalidValue;
     const int n = (int)dsts.size();
+    // uint8 with dword rows everywhere: every brick row a whole number of
+    // dwords (the interior width and twice the ghost width multiples of 4,
+    // or a single brick along x), source rows too, dword-aligned buffers
+    bool dword_rows = false;
+    if constexpr (sizeof(T) == 1) {
+        dword_rows = a.X % 4 == 0 && (2 * a.G[0]) % 4 == 0 &&
+                     (a.nbx == 1 || a.B[0] % 4 == 0) &&
+                     reinterpret_cast<uintptr_t>(a.src) % 4 == 0;
+        for (void* d : dsts) dword_rows = dword_rows && reinterpret_cast<uintptr_t>(d) % 4 == 0;
+    }
     for (int f = 0; f < n; f += kMaxBricks) {
         const int cnt = std::min(kMaxBricks, n - f);
         a.first = f;
         a.count = cnt;
         for (int i = 0; i < cnt; ++i) a.dst[i] = dsts[f + i];
-        hipLaunchKernelGGL((brick_kernel<T>), dim3((unsigned)(chunks * cnt)), dim3(64, 4), 0, s,
-                           a);
+        if (dword_rows)
+            hipLaunchKernelGGL(brick_u8_dword_kernel, dim3((unsigned)(chunks * cnt)), dim3(64, 4),
+                               0, s, a);
+        else
+            hipLaunchKernelGGL((brick_kernel<T>), dim3((unsigned)(chunks * cnt)), dim3(64, 4), 0,
+                               s, a);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -517,7 +517,8 @@ __global__ __launch_bounds__(kNT) void filter_direct_kernel(
     dst[((int64_t)z * a.Y + y) * a.X + x] = finish<T>(acc, a);
 }
 
-// Output regions up to this many cells (k <= 5) take the direct kernel.
+// Output regions up to this many cells (k <= 3: the 27 weights stay in
+// SGPRs) take the direct kernel.
 constexpr int64_t kDirectMaxCells = int64_t(1) << 19;
 
 template <typename T, int K, bool IACC>
@@ -530,7 +531,7 @@ hipError_t launch_k(const FilterJob& j, hipStream_t s)
     {
         const int64_t cells =
             (int64_t)(j.roi[3] - j.roi[0]) * (j.roi[4] - j.roi[1]) * (j.roi[5] - j.roi[2]);
-        if constexpr (K <= 5) {
+        if constexpr (K <= 3) {
             if (cells <= kDirectMaxCells) {
                 const VolDesc a = make_desc(j, 1, g);
                 hipLaunchKernelGGL((filter_direct_kernel<T, K, IACC>),

@@ -242,7 +242,7 @@ def test_c2b_smoothed_noise_gauss5_sampled(orc):
 def test_tiled_vector_path_above_direct_size(orc, dtype, mode):
     """Volumes above the direct kernel's size (2^19 output cells) run the
     tiled vector kernel for k <= 5: every cell against the oracle, float and
-    integer weights; and a small range of the same call (direct kernel) gives
+    integer weights; and a small range of the same call (direct kernel for k <= 3) gives
     the same bytes as the whole-volume (tiled) result on that range -- both sum
     the taps in the same order."""
     from paper_2203_10213_amd import vkt

@@ -28,6 +28,11 @@ CASES = [  # (Z, Y, X), brick (x, y, z), ghost (x, y, z)
     ((3, 4, 2), (8, 8, 8), (2, 1, 4)),          # one brick, ghosts beyond the volume
     ((8, 2, 300), (100, 1, 3), (0, 5, 2)),      # rows wider than a block
     ((10, 20, 30), (2, 2, 2), (1, 0, 1)),       # 750 bricks: several launches
+    # uint8 rows of whole dwords (the dword kernel): source dwords straddled
+    # at a 2-byte offset, x faces inside the first and last dword of a row
+    ((6, 10, 64), (16, 4, 3), (2, 1, 1)),
+    ((5, 7, 40), (8, 3, 2), (4, 2, 1)),         # aligned, faces
+    ((4, 5, 12), (12, 2, 2), (2, 0, 1)),        # one brick along x
 ]
 
 
