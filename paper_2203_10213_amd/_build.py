@@ -29,6 +29,7 @@ VARIANTS = {
         ("vkt_filter_mfma16", ["-DVKT_MFMA_SHAPE=16", "-mllvm", "--amdgpu-mfma-vgpr-form"]),
         ("vkt_filter_mfma32", ["-DVKT_MFMA_SHAPE=32"]),
     ],
+    "vkt_filter_mfma_rp.hip": [("vkt_filter_mfma_rp", ["-mllvm", "--amdgpu-mfma-vgpr-form"])],
 }
 
 

@@ -524,22 +524,34 @@ vktError build_job(const vktStructuredVolume_* dst, const vktStructuredVolume_* 
     return vktNoError;
 }
 
+// k = 5, 7 run on 32x32x16 tiles over row pairs, except where the 16x16x32
+// kernel measured faster on 512^3 volumes (uint8 / uint16 and 6-product
+// float32 with k = 7).  Single and batched launches choose alike, so a batch
+// reproduces its volumes' single launches bit for bit.
+static bool mfma_row_pairs(vktDataFormat f, int k, bool six_products)
+{
+    return k == 5 || (k == 7 && f == vktDataFormatFloat32 && !six_products);
+}
+
 hipError_t launch_filter_mfma(const FilterJob& j, bool six_products, hipStream_t s)
 {
-    return j.k <= 7 ? launch_filter_mfma_s16(j, six_products, s)
-                    : launch_filter_mfma_s32(j, six_products, s);
+    if (j.k >= 9) return launch_filter_mfma_s32(j, six_products, s);
+    return mfma_row_pairs(j.fmt, j.k, six_products) ? launch_filter_mfma_rp(j, six_products, s)
+                                                    : launch_filter_mfma_s16(j, six_products, s);
 }
 
 const void* mfma_batched_kernel(vktDataFormat f, int k, bool six_products, int variant)
 {
-    return k <= 7 ? mfma_batched_kernel_s16(f, k, six_products, variant)
-                  : mfma_batched_kernel_s32(f, k, six_products, variant);
+    if (k >= 9) return mfma_batched_kernel_s32(f, k, six_products, variant);
+    return mfma_row_pairs(f, k, six_products) ? mfma_batched_kernel_rp(f, k, six_products)
+                                              : mfma_batched_kernel_s16(f, k, six_products, variant);
 }
 
 ClassGeom mfma_geom(vktDataFormat f, int k, bool six_products, int variant)
 {
-    return k <= 7 ? mfma_geom_s16(f, k, six_products, variant)
-                  : mfma_geom_s32(f, k, six_products, variant);
+    if (k >= 9) return mfma_geom_s32(f, k, six_products, variant);
+    return mfma_row_pairs(f, k, six_products) ? mfma_geom_rp(f, k, six_products)
+                                              : mfma_geom_s16(f, k, six_products, variant);
 }
 
 int resident_wgs(const void* func)

@@ -205,6 +205,13 @@ hipError_t launch_filter_mfma(const FilterJob& j, bool six_products, hipStream_t
 // The matrix-core kernels are built twice: 16x16x32 tiles for k <= 7 (_s16)
 // and 32x32x16 tiles for k >= 9 (_s32); the unsuffixed functions dispatch.
 hipError_t launch_filter_mfma_s16(const FilterJob& j, bool six_products, hipStream_t s);
+// Single-volume launches with k = 5 or 7: 32x32x16 tiles over pairs of
+// output rows (vkt_filter_mfma_rp.hip).
+hipError_t launch_filter_mfma_rp(const FilterJob& j, bool six_products, hipStream_t s);
+// its persistent batched kernel (one tile shape: both tile-height variants
+// are this kernel) and geometry
+const void* mfma_batched_kernel_rp(vktDataFormat f, int k, bool six_products);
+ClassGeom mfma_geom_rp(vktDataFormat f, int k, bool six_products);
 hipError_t launch_filter_mfma_s32(const FilterJob& j, bool six_products, hipStream_t s);
 // variant: tile height of the batched kernels (0: the default row blocks,
 // 1: the other choice; see kTileVariants)

@@ -42,8 +42,11 @@ CASES = [
     (np.uint16, (7, 35, 66), 5, "float", "fp32"),           # VALU FP32, integer cells
     (np.uint8, (8, 33, 264), 3, "int_u", "auto"),           # dot4 when the region is 4-aligned
     (np.uint8, (6, 20, 67), 5, "int_s", "auto"),            # VALU exact integer (odd rows)
-    (np.float32, (12, 70, 40), 7, "float", "auto"),         # MFMA 16x16 bf16 x6
+    (np.float32, (12, 70, 40), 7, "float", "auto"),         # MFMA row pairs bf16 x6
     (np.uint16, (20, 33, 37), 9, "float", "auto"),          # MFMA 32x32 fp16
+    (np.float32, (10, 131, 70), 7, "float", "splitbf16"),   # MFMA row pairs bf16 x3, 3 tile rows
+    (np.uint8, (9, 70, 45), 5, "float", "auto"),            # MFMA row pairs fp16, k = 5
+    (np.uint16, (8, 67, 99), 7, "float", "auto"),           # MFMA row pairs fp16 x4
 ]
 
 
