@@ -135,7 +135,7 @@ KERNEL_SOURCES = {
     "valu": ["vkt_filter_valu.hip", "vkt_internal.h"],
     "dot4": ["vkt_filter_dot4.hip", "vkt_internal.h"],
     "i8mma": ["vkt_filter_i8mma.hip", "vkt_internal.h"],
-    "mfma": ["vkt_filter_mfma.hip", "vkt_internal.h"],
+    "mfma": ["vkt_filter_mfma.hip", "vkt_filter_mfma_rp.hip", "vkt_mfma_common.h", "vkt_internal.h"],
     "sep": ["vkt_filter_sep.hip", "vkt_internal.h"],
 }
 
