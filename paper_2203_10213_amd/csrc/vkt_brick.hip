@@ -11,12 +11,13 @@
 // batched form directly.
 //
 // One launch covers up to kMaxBricks bricks, whose destination pointers
-// travel in the kernel arguments (no device allocation).  A workgroup copies
-// a run of 64 rows of one brick, its 64 x 4 threads 4 rows at a time, lanes
-// along x; workgroups are numbered so that the same run of all bricks of a
-// launch lands on one XCD.  Interior source reads are contiguous
-// along x, brick writes contiguous; the address mode is applied per
-// coordinate.
+// travel in the kernel arguments (no device allocation), split into 32 low
+// and 16 high address bits so that 512 of them fit the 4 KiB argument block.
+// Bricks whose rows are whole dwords (every format when rows, ghosts and
+// buffers are 4-byte multiples) take the row kernel: 16-byte groups of
+// destination dwords from one 16-byte source load plus one dword, byte
+// aligned with v_alignbyte; other bricks take the cell kernel, lanes along x.
+// The address mode is applied per coordinate.
 #include "vkt_internal.h"
 
 #include <algorithm>
@@ -27,7 +28,7 @@ namespace vkt {
 namespace {
 
 constexpr int kNT = 256;
-constexpr int kMaxBricks = 128;
+constexpr int kMaxBricks = 512;
 
 struct BrickArgs {
     const void* src;
@@ -35,11 +36,23 @@ struct BrickArgs {
     int32_t B[3];         // interior cells per brick
     int32_t G[3];         // ghost cells per side
     int32_t nbx, nby;     // bricks along x, y
-    int32_t first;        // brick index of dst[0]
+    int32_t first;        // brick index of destination 0
     int32_t count;        // bricks of this launch
     int32_t mode;
-    void* dst[kMaxBricks];
+    int32_t rows_per_wg;  // row kernel: brick rows per workgroup
+    int32_t chunks;       // row kernel: workgroups per brick
+    uint32_t dst_lo[kMaxBricks];  // destination addresses, bits 0..31
+    uint16_t dst_hi[kMaxBricks];  // and bits 32..47
 };
+static_assert(sizeof(BrickArgs) <= 4096, "kernel argument block");
+
+// Destination i of the launch as a global-memory pointer (a pointer made
+// from an integer would otherwise be generic and take flat stores).
+template <typename T>
+__device__ inline __attribute__((address_space(1))) T* brick_dst(const BrickArgs& a, int i)
+{
+    return (__attribute__((address_space(1))) T*)((uintptr_t)a.dst_hi[i] << 32 | a.dst_lo[i]);
+}
 
 // Address mode on one axis; -1: outside under border (reads zero).
 __device__ inline int brick_addr(int64_t i, int64_t n, int mode)
@@ -68,7 +81,7 @@ __device__ inline uint32_t xcd_group(uint32_t b, uint32_t n)
     return xcd < rem ? xcd * (q + 1) + idx : rem * (q + 1) + (xcd - rem) * q + idx;
 }
 
-// Rows of a brick per workgroup: 64, i.e. 16 per thread row lane.
+// Cell kernel: rows of a brick per workgroup: 64, i.e. 16 per thread row lane.
 constexpr int kRowsPerWG = 64;
 constexpr int kRowsPerThread = kRowsPerWG / 4;
 
@@ -90,7 +103,7 @@ __global__ __launch_bounds__(kNT) void brick_kernel(BrickArgs a)
     const int64_t r0 = (int64_t)chunk * kRowsPerWG + threadIdx.y;
     if (r0 >= nrows) return;
     const T* __restrict__ src = static_cast<const T*>(a.src);
-    T* __restrict__ dst = static_cast<T*>(a.dst[bl]);
+    __attribute__((address_space(1))) T* __restrict__ dst = brick_dst<T>(a, bl);
     // this thread's rows r0 + 4 i: source row offsets (-1: outside, zeros)
     int64_t soff[kRowsPerThread];
 #pragma unroll
@@ -120,96 +133,149 @@ __global__ __launch_bounds__(kNT) void brick_kernel(BrickArgs a)
     }
 }
 
-// uint8 bricks whose rows are whole dwords (row length, source row length and
-// buffers multiples of 4 bytes): each thread writes whole destination dwords.
-// A dword inside the source row is formed from the two aligned source dwords
-// it straddles and one byte align (v_alignbyte); dwords that reach past an x
-// face of the volume take their four cells through the address mode.  The
-// row offsets of the workgroup's 64 rows are resolved once, into LDS.
-__global__ __launch_bounds__(kNT) void brick_u8_dword_kernel(BrickArgs a)
+// brick_addr in 32-bit arithmetic, for |i| and 2 n below 2^31 (the row
+// kernel's launch condition: every extent plus its ghost width at most 2^30).
+__device__ inline int brick_addr32(int i, int n, int mode)
 {
-    __shared__ int64_t s_row[kRowsPerWG];
+    if (i >= 0 && i < n) return i;
+    if (mode == vktAddressModeClamp) return i < 0 ? 0 : n - 1;
+    if (mode == vktAddressModeWrap) {
+        const int m = i % n;
+        return m < 0 ? m + n : m;
+    }
+    if (mode == vktAddressModeMirror) {
+        const int p = 2 * n;
+        int m = i % p;
+        if (m < 0) m += p;
+        return m < n ? m : p - 1 - m;
+    }
+    return -1;
+}
+
+// Dwords [jlo, jhi) of a brick row whose source bytes lie inside the source
+// row: byte origin ob of the brick row in the source row (negative before
+// it), source row of xb bytes, nd dwords per brick row.  Rows with fewer
+// than 4 such dwords count as all face (jlo = jhi = 0), so that every
+// 16-byte group of a row is whole.
+__host__ __device__ inline void inside_dwords(int64_t ob, int64_t xb, int nd, int& jlo, int& jhi)
+{
+    jlo = ob >= 0 ? 0 : (int)min((int64_t)nd, (3 - ob) / 4);
+    const int64_t last = xb - 4 - ob;  // largest 4 j inside the row
+    jhi = max(jlo, last >= 0 ? (int)min((int64_t)nd, last / 4 + 1) : 0);
+    if (jhi - jlo < 4) jlo = jhi = 0;
+}
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4a4 __attribute__((ext_vector_type(4), aligned(4)));
+
+// Row kernel items (16-byte groups or face dwords) per thread and pass: 3
+// (512^3 into 64^3 bricks + 2 ghosts: uint8 0.082 ms, float32 0.250 ms;
+// with 2 items 0.081 / 0.263 ms, with 4 items 0.082 / 0.258 ms, with 1
+// item 0.091 / 0.307 ms).
+constexpr int kRowItems = 3;
+
+// Row kernel for cells of E bytes: brick rows of whole dwords, source rows
+// and buffers 4-byte aligned.  A workgroup takes rows_per_wg rows of one
+// brick (workgroups of a brick consecutive and, through the XCD numbering,
+// on one XCD); each row is ng 16-byte groups of inside dwords (the last
+// group moved back to end at jhi, so that it rewrites up to 12 bytes of its
+// neighbour with the same values) and nf face dwords.  Group: one 16-byte
+// load at the aligned source dword under its first byte and, when the row
+// is not dword aligned in the source, the dword after it (still inside the
+// source row, as the last inside byte lies in it); v_alignbyte shifts each
+// output dword out of its aligned pair.  Face dword: its 4 / E cells
+// through the address mode, loaded unconditionally (cell 0 of the volume
+// for cells outside under border) and masked.  All loads of a thread are
+// issued before its stores; no LDS, no barrier.
+template <int E>
+__global__ __launch_bounds__(kNT) void brick_rows_kernel(BrickArgs a)
+{
+    constexpr int U = kRowItems;
     const uint32_t logical = xcd_group(blockIdx.x, gridDim.x);
-    const int bl = (int)(logical % (uint32_t)a.count);
-    const int chunk = (int)(logical / (uint32_t)a.count);
+    const int bl = (int)(logical / (uint32_t)a.chunks);
+    const int chunk = (int)(logical - (uint32_t)bl * (uint32_t)a.chunks);
     const int b = a.first + bl;
-    const int bx = b % a.nbx, by = (b / a.nbx) % a.nby, bz = b / (a.nbx * a.nby);
+    const int bx = b % a.nbx, byz = b / a.nbx, by = byz % a.nby, bz = byz / a.nby;
     const int o[3] = {bx * a.B[0] - a.G[0], by * a.B[1] - a.G[1], bz * a.B[2] - a.G[2]};
     const int dx = min(a.B[0], a.X - bx * a.B[0]) + 2 * a.G[0];
     const int dy = min(a.B[1], a.Y - by * a.B[1]) + 2 * a.G[1];
     const int dz = min(a.B[2], a.Z - bz * a.B[2]) + 2 * a.G[2];
-    const int64_t nrows = (int64_t)dy * dz;
-    const int64_t r0 = (int64_t)chunk * kRowsPerWG;
-    if (r0 >= nrows) return;  // the whole workgroup (before any barrier)
-    const int rows = (int)min((int64_t)kRowsPerWG, nrows - r0);
-    const int t = threadIdx.x + 64 * threadIdx.y;
-    if (t < rows) {
-        const int64_t r = r0 + t;
-        const int z = (int)(r / dy), y = (int)(r - (int64_t)z * dy);
-        const int sy = brick_addr((int64_t)o[1] + y, a.Y, a.mode);
-        const int sz = brick_addr((int64_t)o[2] + z, a.Z, a.mode);
-        s_row[t] = (sy | sz) >= 0 ? ((int64_t)sz * a.Y + sy) * a.X : -1;
-    }
-    __syncthreads();
+    const int nrows = dy * dz;  // the host keeps brick dwords below 2^31
+    const int r0 = chunk * a.rows_per_wg;
+    if (r0 >= nrows) return;
+    const int rows = min(a.rows_per_wg, nrows - r0);
+    const int nd = (int)((int64_t)dx * E / 4);
+    const int64_t ob = (int64_t)o[0] * E;
+    const int sh = (int)(ob & 3);
+    int jlo, jhi;
+    inside_dwords(ob, (int64_t)a.X * E, nd, jlo, jhi);
+    const int ni = jhi - jlo, ng = (ni + 3) / 4, nf = nd - ni, per_row = ng + nf;
     const uint8_t* __restrict__ src = static_cast<const uint8_t*>(a.src);
-    uint32_t* __restrict__ dst = static_cast<uint32_t*>(a.dst[bl]) + r0 * (dx / 4);
-    const int nd = dx / 4;
-    // Dword j of a row covers source x in [o[0] + 4 j, o[0] + 4 j + 4); it
-    // lies inside the source row for j in [jlo, jhi), the same for every row
-    // of the brick.
-    const int jlo = o[0] >= 0 ? 0 : min(nd, (3 - o[0]) / 4);
-    const int last = a.X - 4 - o[0];  // largest 4 j inside the row
-    const int jhi = max(jlo, last >= 0 ? min(nd, last / 4 + 1) : 0);
-    const int ni = jhi - jlo, nf = nd - ni;
-    // Interior dwords, in batches of kBatch per thread: all loads of a batch
-    // are issued before its stores.  A dword at byte offset p is the aligned
-    // pair (lo, hi) around it shifted by p & 3 bytes (v_alignbyte; shift 0
-    // gives lo).  Rows outside the volume under border read as zero.
-    constexpr int kBatch = 8;
-    const int n = rows * ni;
-    for (int i0 = t; i0 < n; i0 += kBatch * kNT) {
-        uint32_t lo[kBatch], hi[kBatch], sh[kBatch];
+    __attribute__((address_space(1))) uint32_t* __restrict__ dst = brick_dst<uint32_t>(a, bl);
+    const int t = threadIdx.x + 64 * threadIdx.y;
+    const int n = rows * per_row;
+    for (int i0 = t; i0 < n; i0 += U * kNT) {
+        u32x4 w[U];
+        uint32_t e[U];
+        int di[U];
+        bool face[U];
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
+        for (int u = 0; u < U; ++u) {
             const int i = i0 + u * kNT;
-            lo[u] = hi[u] = sh[u] = 0;
-            const int rl = i < n ? i / ni : 0;
-            const int64_t so = s_row[rl];
-            if (i < n && so >= 0) {
-                const int64_t p = so + o[0] + 4 * (jlo + (i - rl * ni));
-                const uint32_t* q = reinterpret_cast<const uint32_t*>(src + (p & ~int64_t(3)));
-                sh[u] = (uint32_t)(p & 3);
-                lo[u] = q[0];
-                // the next aligned dword is inside the row when p is not
-                // aligned (rows end on a dword boundary)
-                if (sh[u]) hi[u] = q[1];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            const int i = i0 + u * kNT;
+            w[u] = u32x4{0u, 0u, 0u, 0u};
+            e[u] = 0u;
+            di[u] = -1;
+            face[u] = false;
             if (i < n) {
-                const int rl = i / ni;
-                dst[(int64_t)rl * nd + jlo + (i - rl * ni)] =
-                    __builtin_amdgcn_alignbyte(hi[u], lo[u], sh[u]);
+                const int rl = i / per_row, k = i - rl * per_row;
+                const int r = r0 + rl;
+                const int z = r / dy, y = r - z * dy;
+                const int sy = brick_addr32(o[1] + y, a.Y, a.mode);
+                const int sz = brick_addr32(o[2] + z, a.Z, a.mode);
+                // source row start in cells; -1: outside under border
+                const int64_t so = (sy | sz) >= 0 ? ((int64_t)sz * a.Y + sy) * a.X : -1;
+                if (k < ng) {
+                    const int j0 = jlo + min(4 * k, ni - 4);
+                    di[u] = r * nd + j0;
+                    if (so >= 0) {
+                        const uint8_t* q = src + (so * E + ob - sh + 4 * (int64_t)j0);
+                        w[u] = *reinterpret_cast<const u32x4a4*>(q);
+                        if (sh) e[u] = *reinterpret_cast<const uint32_t*>(q + 16);
+                    }
+                } else {
+                    const int jf = k - ng;
+                    const int j = jf < jlo ? jf : jhi + (jf - jlo);
+                    di[u] = r * nd + j;
+                    face[u] = true;
+                    uint32_t v = 0u;
+#pragma unroll
+                    for (int c = 0; c < 4 / E; ++c) {
+                        const int cx = brick_addr32(o[0] + j * (4 / E) + c, a.X, a.mode);
+                        const bool ok = so >= 0 && cx >= 0;
+                        const int64_t ci = ok ? so + cx : 0;
+                        uint32_t cell;
+                        if constexpr (E == 1) cell = src[ci];
+                        else if constexpr (E == 2) cell = reinterpret_cast<const uint16_t*>(src)[ci];
+                        else cell = reinterpret_cast<const uint32_t*>(src)[ci];
+                        v |= (ok ? cell : 0u) << (8 * E * c);
+                    }
+                    w[u].x = v;
+                }
             }
         }
-    }
-    // Dwords that reach past an x face: four cells through the address mode.
-    const int m = rows * nf;
-    for (int i = t; i < m; i += kNT) {
-        const int rl = i / nf, jf = i - rl * nf;
-        const int j = jf < jlo ? jf : jhi + (jf - jlo);
-        const int64_t so = s_row[rl];
-        const int sx = o[0] + 4 * j;
-        uint32_t v = 0;
-        if (so >= 0) {
-            for (int c = 0; c < 4; ++c) {
-                const int cx = brick_addr((int64_t)sx + c, a.X, a.mode);
-                if (cx >= 0) v |= (uint32_t)src[so + cx] << (8 * c);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (di[u] < 0) continue;
+            if (face[u]) {
+                dst[di[u]] = w[u].x;
+                continue;
             }
+            const u32x4 v{__builtin_amdgcn_alignbyte(w[u].y, w[u].x, sh),
+                          __builtin_amdgcn_alignbyte(w[u].z, w[u].y, sh),
+                          __builtin_amdgcn_alignbyte(w[u].w, w[u].z, sh),
+                          __builtin_amdgcn_alignbyte(e[u], w[u].w, sh)};
+            *reinterpret_cast<__attribute__((address_space(1))) u32x4a4*>(dst + di[u]) = v;
         }
-        dst[(int64_t)rl * nd + j] = v;
     }
 }
 
@@ -233,32 +299,71 @@ bool valid_brick_args(const vktStructuredVolume_* src, const int32_t B[3], const
     return true;
 }
 
+// Row kernel geometry: the largest per-row item count (16-byte groups plus
+// face dwords) over the bricks along x, for cells of E bytes.  Only bricks
+// within reach of a face differ from the interior ones, so those and one
+// interior brick are visited.
+int max_row_items(const BrickArgs& a, int E)
+{
+    const int reach = a.G[0] / a.B[0] + 2;
+    int best = 1;
+    for (int bx = 0; bx < a.nbx; ++bx) {
+        if (bx > reach + 1 && bx < a.nbx - 2 - reach) bx = a.nbx - 2 - reach;
+        const int64_t ob = ((int64_t)bx * a.B[0] - a.G[0]) * E;
+        const int dx = std::min(a.B[0], a.X - bx * a.B[0]) + 2 * a.G[0];
+        const int nd = (int)((int64_t)dx * E / 4);
+        int jlo, jhi;
+        inside_dwords(ob, (int64_t)a.X * E, nd, jlo, jhi);
+        best = std::max(best, (jhi - jlo + 3) / 4 + nd - (jhi - jlo));
+    }
+    return best;
+}
+
 template <typename T>
 hipError_t launch_bricks(BrickArgs& a, const std::vector<void*>& dsts, hipStream_t s)
 {
+    constexpr int E = sizeof(T);
+    const int64_t dx_max = std::min(a.B[0], a.X) + 2 * (int64_t)a.G[0];
     const int64_t rows_max =
         (int64_t)(std::min(a.B[1], a.Y) + 2 * a.G[1]) * (std::min(a.B[2], a.Z) + 2 * a.G[2]);
-    const int64_t chunks = (rows_max + kRowsPerWG - 1) / kRowsPerWG;
-    if (chunks * kMaxBricks > INT32_MAX) return hipErrorInvalidValue;
     const int n = (int)dsts.size();
-    // uint8 with dword rows everywhere: every brick row a whole number of
-    // dwords (the interior width and twice the ghost width multiples of 4,
-    // or a single brick along x), source rows too, dword-aligned buffers
-    bool dword_rows = false;
-    if constexpr (sizeof(T) == 1) {
-        dword_rows = a.X % 4 == 0 && (2 * a.G[0]) % 4 == 0 &&
-                     (a.nbx == 1 || a.B[0] % 4 == 0) &&
-                     reinterpret_cast<uintptr_t>(a.src) % 4 == 0;
-        for (void* d : dsts) dword_rows = dword_rows && reinterpret_cast<uintptr_t>(d) % 4 == 0;
+    // destination addresses travel as 48 bits
+    for (void* d : dsts)
+        if (reinterpret_cast<uintptr_t>(d) >> 48) return hipErrorInvalidValue;
+    // row kernel: every brick row a whole number of dwords (the interior and
+    // twice the ghost width in bytes multiples of 4, or a single brick along
+    // x), source rows too, dword-aligned buffers, brick dwords below 2^31
+    bool rows = (int64_t)a.X * E % 4 == 0 && 2 * (int64_t)a.G[0] * E % 4 == 0 &&
+                (a.nbx == 1 || (int64_t)a.B[0] * E % 4 == 0) &&
+                reinterpret_cast<uintptr_t>(a.src) % 4 == 0 &&
+                dx_max * E / 4 * rows_max < ((int64_t)1 << 31);
+    // and 32-bit coordinates: every extent plus its ghost width within 2^30
+    const int64_t ext[3] = {a.X, a.Y, a.Z};
+    for (int k = 0; k < 3; ++k) rows = rows && ext[k] + a.G[k] <= ((int64_t)1 << 30);
+    for (void* d : dsts) rows = rows && reinterpret_cast<uintptr_t>(d) % 4 == 0;
+    int64_t chunks;
+    if (rows) {
+        // one pass per workgroup
+        a.rows_per_wg = std::max(1, kRowItems * kNT / max_row_items(a, E));
+        chunks = (rows_max + a.rows_per_wg - 1) / a.rows_per_wg;
+    } else {
+        a.rows_per_wg = kRowsPerWG;
+        chunks = (rows_max + kRowsPerWG - 1) / kRowsPerWG;
     }
+    if (chunks * kMaxBricks > INT32_MAX) return hipErrorInvalidValue;
+    a.chunks = (int32_t)chunks;
     for (int f = 0; f < n; f += kMaxBricks) {
         const int cnt = std::min(kMaxBricks, n - f);
         a.first = f;
         a.count = cnt;
-        for (int i = 0; i < cnt; ++i) a.dst[i] = dsts[f + i];
-        if (dword_rows)
-            hipLaunchKernelGGL(brick_u8_dword_kernel, dim3((unsigned)(chunks * cnt)), dim3(64, 4),
-                               0, s, a);
+        for (int i = 0; i < cnt; ++i) {
+            const uintptr_t d = reinterpret_cast<uintptr_t>(dsts[f + i]);
+            a.dst_lo[i] = (uint32_t)d;
+            a.dst_hi[i] = (uint16_t)(d >> 32);
+        }
+        if (rows)
+            hipLaunchKernelGGL(brick_rows_kernel<E>, dim3((unsigned)(chunks * cnt)), dim3(64, 4), 0,
+                               s, a);
         else
             hipLaunchKernelGGL((brick_kernel<T>), dim3((unsigned)(chunks * cnt)), dim3(64, 4), 0,
                                s, a);

@@ -28,11 +28,15 @@ CASES = [  # (Z, Y, X), brick (x, y, z), ghost (x, y, z)
     ((3, 4, 2), (8, 8, 8), (2, 1, 4)),          # one brick, ghosts beyond the volume
     ((8, 2, 300), (100, 1, 3), (0, 5, 2)),      # rows wider than a block
     ((10, 20, 30), (2, 2, 2), (1, 0, 1)),       # 750 bricks: several launches
-    # uint8 rows of whole dwords (the dword kernel): source dwords straddled
-    # at a 2-byte offset, x faces inside the first and last dword of a row
+    # rows of whole dwords (the row kernel; every float32 case): source
+    # dwords straddled at a 2-byte offset, x faces inside the first and last
+    # dword of a row
     ((6, 10, 64), (16, 4, 3), (2, 1, 1)),
     ((5, 7, 40), (8, 3, 2), (4, 2, 1)),         # aligned, faces
     ((4, 5, 12), (12, 2, 2), (2, 0, 1)),        # one brick along x
+    # uint16 rows of whole dwords at a 2-byte source offset (odd ghost width)
+    ((6, 9, 50), (10, 3, 4), (3, 1, 2)),
+    ((3, 5, 8), (8, 5, 3), (6, 0, 0)),          # rows with fewer than 4 inside dwords
 ]
 
 
@@ -133,3 +137,16 @@ def test_invalid_arguments():
     finally:
         for h in hb + hq + [hs, ho]:
             vkt.vktStructuredVolumeDestroy(h)
+
+
+def test_bench_workload_bricks(orc):
+    """The 512^3 uint8 phantom into 64^3 bricks with 2 ghost cells under
+    clamp (512 bricks, one launch), every brick bit-exact."""
+    from paper_2203_10213_amd import synth, vkt
+    src = synth.ct_phantom_u8(512, synth.SEEDS["c2a"])
+    got = vkt.brick_decompose(to_device(src), (64, 64, 64), (2, 2, 2), "clamp")
+    vkt.vktSynchronize()
+    want = orc.brick_decompose(src, (64, 64, 64), (2, 2, 2), "clamp")
+    assert len(got) == len(want) == 512
+    for i, (a, b) in enumerate(zip(got, want)):
+        assert np.array_equal(a.cpu().numpy(), b), f"brick {i}"
