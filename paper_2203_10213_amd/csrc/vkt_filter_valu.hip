@@ -473,10 +473,17 @@ __global__ __launch_bounds__(kNT) void filter_valu_batched_kernel(BatchArgs b)
     }
 }
 
+// Output regions up to this many cells (k <= 3: the 27 weights stay in
+// SGPRs) take the direct kernel, in workgroups of kDirectBX x kDirectBY.
+constexpr int64_t kDirectMaxCells = int64_t(1) << 19;
+constexpr int kDirectBX = 64, kDirectBY = kNT / kDirectBX;
+
 // Small output regions: one thread per output cell reading its k^3 taps
 // straight from memory (the whole source is cache resident at these sizes),
 // with no LDS staging and no barriers, so a 64^3 volume is 1024 workgroups in
-// one wave of the device instead of a few dozen tile-slabs.  Taps are summed
+// one wave of the device instead of a few dozen tile-slabs.  Workgroups of
+// 64 x 4 threads cover 64 x 4 outputs of one plane (grid: x runs, y runs,
+// planes), so a thread finds its cell without divisions.  Taps are summed
 // in the tiled kernel's order (filter plane, row, column).
 template <typename T, int K, bool IACC>
 __global__ __launch_bounds__(kNT) void filter_direct_kernel(
@@ -484,11 +491,10 @@ __global__ __launch_bounds__(kNT) void filter_direct_kernel(
 {
     using Acc = typename AccT<IACC>::type;
     constexpr int R = (K - 1) / 2;
-    const int64_t rx = a.rx1 - a.rx0, ry = a.ry1 - a.ry0, rz = a.rz1 - a.rz0;
-    const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
-    if (i >= rx * ry * rz) return;
-    const int x = a.rx0 + (int)(i % rx), y = a.ry0 + (int)((i / rx) % ry),
-              z = a.rz0 + (int)(i / (rx * ry));
+    const int x = a.rx0 + (int)blockIdx.x * kDirectBX + (int)threadIdx.x;
+    const int y = a.ry0 + (int)blockIdx.y * kDirectBY + (int)threadIdx.y;
+    const int z = a.rz0 + (int)blockIdx.z;
+    if (x >= a.rx1 || y >= a.ry1) return;
     int xs[K], ys[K], zs[K];  // coordinates through the address mode; -1: zero
 #pragma unroll
     for (int t = 0; t < K; ++t) {
@@ -517,9 +523,6 @@ __global__ __launch_bounds__(kNT) void filter_direct_kernel(
     dst[((int64_t)z * a.Y + y) * a.X + x] = finish<T>(acc, a);
 }
 
-// Output regions up to this many cells (k <= 3: the 27 weights stay in
-// SGPRs) take the direct kernel.
-constexpr int64_t kDirectMaxCells = int64_t(1) << 19;
 
 template <typename T, int K, bool IACC>
 hipError_t launch_k(const FilterJob& j, hipStream_t s)
@@ -532,11 +535,14 @@ hipError_t launch_k(const FilterJob& j, hipStream_t s)
         const int64_t cells =
             (int64_t)(j.roi[3] - j.roi[0]) * (j.roi[4] - j.roi[1]) * (j.roi[5] - j.roi[2]);
         if constexpr (K <= 3) {
-            if (cells <= kDirectMaxCells) {
+            const int RY = j.roi[4] - j.roi[1], RZ = j.roi[5] - j.roi[2];
+            const int gy = (RY + kDirectBY - 1) / kDirectBY;
+            if (cells <= kDirectMaxCells && gy <= 65535 && RZ <= 65535) {
                 const VolDesc a = make_desc(j, 1, g);
+                const int gx = (j.roi[3] - j.roi[0] + kDirectBX - 1) / kDirectBX;
                 hipLaunchKernelGGL((filter_direct_kernel<T, K, IACC>),
-                                   dim3((unsigned)((cells + kNT - 1) / kNT)), dim3(kNT), 0, s, a,
-                                   w);
+                                   dim3((unsigned)gx, (unsigned)gy, (unsigned)RZ),
+                                   dim3(kDirectBX, kDirectBY), 0, s, a, w);
                 return hipGetLastError();
             }
         }
