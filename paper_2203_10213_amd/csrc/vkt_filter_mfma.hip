@@ -279,6 +279,9 @@ __device__ void mfma_tile(const VolDesc& a, const float* __restrict__ w, int til
         // (float32 volumes on 32x32 tiles, short of registers, read each
         // group's segments just before its products: measured faster there)
         constexpr bool PIPE = C::SHAPE == 16 || std::is_same<T, uint16_t>::value;
+        // the products at raised wave priority (the issue arbiter prefers
+        // this wave's matrix work over other waves' staging and epilogues)
+        __builtin_amdgcn_s_setprio(1);
         load_seg(0, seg[0]);
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
@@ -308,6 +311,7 @@ __device__ void mfma_tile(const VolDesc& a, const float* __restrict__ w, int til
                         A[st][PC::prod[pr][0]], B[q][PC::prod[pr][1]], acc[yb * C::WS + st]);
         }
         // the next plane's cells are split and staged after the products
+        __builtin_amdgcn_s_setprio(0);
         __builtin_amdgcn_sched_barrier(0);
         put(cur ^ 1);
 

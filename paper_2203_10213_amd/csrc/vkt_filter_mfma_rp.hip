@@ -305,6 +305,10 @@ __device__ void rp_tile(const VolDesc& a, const float* __restrict__ w, int tile,
                     sg[ps][h] = *reinterpret_cast<const u32x4*>(&lds[P][ps][off + 8 * h]);
         };
         u32x4 seg[2][PC::PS][2];
+        // the products at raised wave priority: the issue arbiter prefers
+        // this wave's matrix instructions over the other wave's staging and
+        // epilogue work (1024^3 7^3: 3.18 -> 3.08 ms)
+        __builtin_amdgcn_s_setprio(1);
         read_seg(0, seg[0]);
 #pragma unroll
         for (int q = 0; q < C::NCH; ++q) {
@@ -341,6 +345,7 @@ __device__ void rp_tile(const VolDesc& a, const float* __restrict__ w, int tile,
             }
         }
         // the next plane's cells are split and staged after the products
+        __builtin_amdgcn_s_setprio(0);
         __builtin_amdgcn_sched_barrier(0);
         put(std::integral_constant<int, STAGE>{}, std::integral_constant<int, P ^ 1>{});
 
