@@ -352,6 +352,18 @@ vktError vktGetSeparable(int* enable);
  * ApplyFilterRange); the batched form uses the dot products. */
 vktError vktSetInt8Matrix(int enable);
 vktError vktGetInt8Matrix(int* enable);
+/* Row-pair threshold (per thread; default 2^24 cells, or the
+ * VKT_ROW_PAIR_MIN_CELLS environment variable).  Matrix-core jobs with k = 5,
+ * and float32 k = 7 with 3 products, whose output region (the whole volume,
+ * or the ROI of a range call) has more than `cells` cells run on the 32x32x16
+ * row-pair kernel; smaller ones run on 16x16x32 tiles, which measured faster
+ * for batches of volumes up to 256^3.  Both compute the same split products;
+ * the summation order differs, so float results may differ by rounding
+ * (within the stated tolerances).  A batch chooses per volume exactly as the
+ * single call would.  Errors: vktInvalidValue for cells < 0 or a NULL
+ * out-pointer. */
+vktError vktSetRowPairMinCells(int64_t cells);
+vktError vktGetRowPairMinCells(int64_t* cells);
 
 /* *separable = 1 if the filter's weights are rank 1 (as above), else 0. */
 vktError vktFilterIsSeparable(vktFilter filter, int* separable);

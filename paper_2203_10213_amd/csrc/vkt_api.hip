@@ -23,6 +23,7 @@ struct ThreadState {
     bool autotune = false;
     bool separable = false;
     bool int8_matrix = false;
+    int64_t row_pair_min_cells = int64_t(1) << 24;
     bool init = false;
 };
 thread_local ThreadState t_state;
@@ -39,6 +40,11 @@ ThreadState& state()
         if (const char* p = std::getenv("VKT_AUTOTUNE")) t_state.autotune = p[0] == '1';
         if (const char* p = std::getenv("VKT_SEPARABLE")) t_state.separable = p[0] == '1';
         if (const char* p = std::getenv("VKT_INT8_MATRIX")) t_state.int8_matrix = p[0] == '1';
+        if (const char* p = std::getenv("VKT_ROW_PAIR_MIN_CELLS")) {
+            char* end = nullptr;
+            const long long v = std::strtoll(p, &end, 10);
+            if (end != p && v >= 0) t_state.row_pair_min_cells = v;
+        }
     }
     return t_state;
 }
@@ -395,6 +401,7 @@ vktPrecision thread_precision() { return state().precision; }
 bool thread_autotune() { return state().autotune; }
 bool thread_separable() { return state().separable; }
 bool thread_int8_matrix() { return state().int8_matrix; }
+int64_t thread_row_pair_min_cells() { return state().row_pair_min_cells; }
 
 VolDesc make_desc(const FilterJob& j, int tz, ClassGeom g)
 {
@@ -525,33 +532,40 @@ vktError build_job(const vktStructuredVolume_* dst, const vktStructuredVolume_* 
 }
 
 // k = 5, 7 run on 32x32x16 tiles over row pairs, except where the 16x16x32
-// kernel measured faster on 512^3 volumes (uint8 / uint16 and 6-product
-// float32 with k = 7).  Single and batched launches choose alike, so a batch
-// reproduces its volumes' single launches bit for bit.
-static bool mfma_row_pairs(vktDataFormat f, int k, bool six_products)
+// kernel measured faster: uint8 / uint16 and 6-product float32 with k = 7 on
+// 512^3 volumes, and output regions of at most the thread's row-pair
+// threshold (default 2^24 cells: 256 uneven uint16 volumes of up to 256^3 in
+// one batch take 2.59 ms with the 16x16x32 kernel's 16-row tiles against
+// 2.81 ms with row pairs for k = 5).  Single and batched launches choose
+// alike, so a batch reproduces its volumes' single launches bit for bit.
+bool mfma_row_pairs(const FilterJob& j, bool six_products)
 {
-    return k == 5 || (k == 7 && f == vktDataFormatFloat32 && !six_products);
+    const int64_t cells =
+        (int64_t)(j.roi[3] - j.roi[0]) * (j.roi[4] - j.roi[1]) * (j.roi[5] - j.roi[2]);
+    return (j.k == 5 || (j.k == 7 && j.fmt == vktDataFormatFloat32 && !six_products)) &&
+           cells > state().row_pair_min_cells;
 }
 
 hipError_t launch_filter_mfma(const FilterJob& j, bool six_products, hipStream_t s)
 {
     if (j.k >= 9) return launch_filter_mfma_s32(j, six_products, s);
-    return mfma_row_pairs(j.fmt, j.k, six_products) ? launch_filter_mfma_rp(j, six_products, s)
-                                                    : launch_filter_mfma_s16(j, six_products, s);
+    return mfma_row_pairs(j, six_products) ? launch_filter_mfma_rp(j, six_products, s)
+                                           : launch_filter_mfma_s16(j, six_products, s);
 }
 
-const void* mfma_batched_kernel(vktDataFormat f, int k, bool six_products, int variant)
+const void* mfma_batched_kernel(vktDataFormat f, int k, bool six_products, bool row_pairs,
+                                int variant)
 {
     if (k >= 9) return mfma_batched_kernel_s32(f, k, six_products, variant);
-    return mfma_row_pairs(f, k, six_products) ? mfma_batched_kernel_rp(f, k, six_products)
-                                              : mfma_batched_kernel_s16(f, k, six_products, variant);
+    return row_pairs ? mfma_batched_kernel_rp(f, k, six_products)
+                     : mfma_batched_kernel_s16(f, k, six_products, variant);
 }
 
-ClassGeom mfma_geom(vktDataFormat f, int k, bool six_products, int variant)
+ClassGeom mfma_geom(vktDataFormat f, int k, bool six_products, bool row_pairs, int variant)
 {
     if (k >= 9) return mfma_geom_s32(f, k, six_products, variant);
-    return mfma_row_pairs(f, k, six_products) ? mfma_geom_rp(f, k, six_products)
-                                              : mfma_geom_s16(f, k, six_products, variant);
+    return row_pairs ? mfma_geom_rp(f, k, six_products)
+                     : mfma_geom_s16(f, k, six_products, variant);
 }
 
 int resident_wgs(const void* func)
@@ -817,6 +831,20 @@ vktError vktGetInt8Matrix(int* enable)
 {
     if (!enable) return vktInvalidValue;
     *enable = state().int8_matrix ? 1 : 0;
+    return vktNoError;
+}
+
+vktError vktSetRowPairMinCells(int64_t cells)
+{
+    if (cells < 0) return vktInvalidValue;
+    state().row_pair_min_cells = cells;
+    return vktNoError;
+}
+
+vktError vktGetRowPairMinCells(int64_t* cells)
+{
+    if (!cells) return vktInvalidValue;
+    *cells = state().row_pair_min_cells;
     return vktNoError;
 }
 

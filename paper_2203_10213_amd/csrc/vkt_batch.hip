@@ -34,8 +34,9 @@ namespace vkt {
 namespace {
 
 struct ClassKey {
-    // path 0 = vector ALU (flag: int accumulate), 1 = matrix (flag: 6
-    // products), 2 = 8-bit dot products (flag: signed weights)
+    // path 0 = vector ALU (flag: int accumulate), 1 = matrix (flag bit 0: 6
+    // products, bit 1: row-pair kernel), 2 = 8-bit dot products (flag:
+    // signed weights)
     int fmt, k, path, flag;
     bool operator<(const ClassKey& o) const
     {
@@ -48,14 +49,16 @@ struct ClassKey {
 const void* class_kernel(const ClassKey& c, int variant)
 {
     if (c.path == 2) return dot4_batched_kernel(c.k, c.flag != 0, variant);
-    return c.path ? mfma_batched_kernel((vktDataFormat)c.fmt, c.k, c.flag != 0, variant)
+    return c.path ? mfma_batched_kernel((vktDataFormat)c.fmt, c.k, (c.flag & 1) != 0,
+                                        (c.flag & 2) != 0, variant)
                   : valu_batched_kernel((vktDataFormat)c.fmt, c.k, c.flag != 0, variant);
 }
 
 ClassGeom class_geom(const ClassKey& c, int variant)
 {
     if (c.path == 2) return dot4_geom(c.k, variant);
-    return c.path ? mfma_geom((vktDataFormat)c.fmt, c.k, c.flag != 0, variant)
+    return c.path ? mfma_geom((vktDataFormat)c.fmt, c.k, (c.flag & 1) != 0, (c.flag & 2) != 0,
+                              variant)
                   : valu_geom(c.k, variant);
 }
 
@@ -493,6 +496,7 @@ vktError prepare_batch(int32_t n, const vktStructuredVolume* dst, const vktStruc
     sig.push_back((uintptr_t)n);
     sig.push_back((uintptr_t)mode);
     sig.push_back((uintptr_t)prec);
+    sig.push_back((uintptr_t)thread_row_pair_min_cells());
     sig.push_back((uintptr_t)stream);
     for (int i = 0; i < n; ++i) {
         bool mfma = false, six = false;
@@ -502,7 +506,8 @@ vktError prepare_batch(int32_t n, const vktStructuredVolume* dst, const vktStruc
         if (e != vktNoError) return e;
         const FilterJob& j = tr[i].j;
         tr[i].f = filters[i];
-        if (mfma) tr[i].key = ClassKey{(int)j.fmt, j.k, 1, six ? 1 : 0};
+        if (mfma)
+            tr[i].key = ClassKey{(int)j.fmt, j.k, 1, (six ? 1 : 0) | (mfma_row_pairs(j, six) ? 2 : 0)};
         else if (j.dot4) tr[i].key = ClassKey{(int)j.fmt, j.k, 2, j.q_signed ? 1 : 0};
         else tr[i].key = ClassKey{(int)j.fmt, j.k, 0, j.int_acc ? 1 : 0};
         sig.push_back((uintptr_t)j.src);

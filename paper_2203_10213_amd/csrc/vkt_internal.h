@@ -228,8 +228,13 @@ ClassGeom mfma_geom_s32(vktDataFormat f, int k, bool six_products, int variant =
 constexpr int kTileVariants = 2;
 const void* valu_batched_kernel(vktDataFormat f, int k, bool int_acc, int variant = 0);
 ClassGeom valu_geom(int k, int variant = 0);
-const void* mfma_batched_kernel(vktDataFormat f, int k, bool six_products, int variant = 0);
-ClassGeom mfma_geom(vktDataFormat f, int k, bool six_products, int variant = 0);
+// Matrix-core job on the row-pair kernel (k = 5 and 3-product float32
+// k = 7, output regions above the thread's row-pair threshold) rather than on
+// 16x16x32 tiles; the batched form takes the choice per volume, as its class.
+bool mfma_row_pairs(const FilterJob& j, bool six_products);
+const void* mfma_batched_kernel(vktDataFormat f, int k, bool six_products, bool row_pairs,
+                                int variant = 0);
+ClassGeom mfma_geom(vktDataFormat f, int k, bool six_products, bool row_pairs, int variant = 0);
 // Fill in the descriptor fields the kernels derive from a FilterJob.
 VolDesc make_desc(const FilterJob& j, int tz, ClassGeom g);
 // Workgroups of 256 threads of `func` resident on the whole current device
@@ -257,5 +262,6 @@ vktPrecision thread_precision();
 bool thread_autotune();
 bool thread_separable();
 bool thread_int8_matrix();
+int64_t thread_row_pair_min_cells();
 
 }  // namespace vkt

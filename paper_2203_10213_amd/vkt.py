@@ -70,6 +70,8 @@ SIGNATURES = {
     "vktGetSeparable": [ctypes.POINTER(ctypes.c_int)],
     "vktSetInt8Matrix": [ctypes.c_int],
     "vktGetInt8Matrix": [ctypes.POINTER(ctypes.c_int)],
+    "vktSetRowPairMinCells": [ctypes.c_int64],
+    "vktGetRowPairMinCells": [ctypes.POINTER(ctypes.c_int64)],
     "vktFilterIsSeparable": [_P, ctypes.POINTER(ctypes.c_int)],
     "vktGetFilterPath": [_P, _P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _PI],
     "vktSetStream": [_P],
@@ -337,6 +339,16 @@ def vktGetInt8Matrix():
     v = ctypes.c_int()
     _ok(lib().vktGetInt8Matrix(ctypes.byref(v)), "vktGetInt8Matrix")
     return bool(v.value)
+
+
+def vktSetRowPairMinCells(cells):
+    _ok(lib().vktSetRowPairMinCells(int(cells)), "vktSetRowPairMinCells")
+
+
+def vktGetRowPairMinCells():
+    v = ctypes.c_int64()
+    _ok(lib().vktGetRowPairMinCells(ctypes.byref(v)), "vktGetRowPairMinCells")
+    return v.value
 
 
 def vktFilterIsSeparable(filt):

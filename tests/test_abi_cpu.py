@@ -137,3 +137,18 @@ def test_stream_is_thread_local(vkt):
     assert seen["s"] is None and vkt.vktGetStream() == 0x1234
     vkt.vktSetStream(None)
     assert vkt.vktGetStream() is None
+
+
+def test_row_pair_threshold_setting(vkt):
+    """Per-thread state only: no device work."""
+    old = vkt.vktGetRowPairMinCells()
+    assert old >= 0
+    try:
+        vkt.vktSetRowPairMinCells(12345)
+        assert vkt.vktGetRowPairMinCells() == 12345
+        with pytest.raises(vkt.VktError) as e:
+            vkt.vktSetRowPairMinCells(-1)
+        assert e.value.code == vkt.vktInvalidValue
+        assert vkt.lib().vktGetRowPairMinCells(None) == vkt.vktInvalidValue
+    finally:
+        vkt.vktSetRowPairMinCells(old)

@@ -88,6 +88,31 @@ MIXED = [((9, 33, 65), np.uint16, 3, "float"), ((40, 37, 90), np.uint16, 5, "flo
          ((5, 129, 40), np.uint16, 3, "int"), ((1, 1, 1), np.float32, 7, "float")]
 
 
+def test_row_pair_threshold_splits_classes(orc):
+    """With the row-pair threshold at 40 000 cells, the larger k = 5 and
+    3-product float32 k = 7 volumes of a batch run on the row-pair batched
+    kernel and the smaller ones on 16x16x32 tiles; every output equals its
+    single call under the same threshold bit for bit, and the oracle."""
+    from paper_2203_10213_amd import vkt
+    specs = [((20, 50, 70), np.uint16, 5, "float"), ((9, 20, 33), np.uint16, 5, "float"),
+             ((17, 66, 45), np.float32, 7, "float"), ((6, 20, 30), np.float32, 7, "float"),
+             ((21, 40, 64), np.uint8, 5, "float"), ((4, 5, 6), np.uint8, 5, "float")]
+    rp = vkt.vktGetRowPairMinCells()
+    vkt.vktSetRowPairMinCells(40000)
+    vkt.vktSetPrecision("splitbf16")
+    b = Batch(specs, 23)
+    try:
+        outs = b.run("wrap")
+        for i, x in enumerate(b.items):
+            single = b.single(i, "wrap")
+            assert np.array_equal(outs[i].view(np.uint8), single.view(np.uint8)), i
+            check_against_oracle(orc, x["src"], x["w"], "wrap", outs[i], divisor=x["D"],
+                                 what=f"threshold batch item {i}")
+    finally:
+        b.close()
+        vkt.vktSetRowPairMinCells(rp)
+
+
 @pytest.mark.parametrize("mode", ["clamp", "mirror", "border"])
 def test_batch_equals_single_and_oracle(orc, mode):
     b = Batch(MIXED, 11)

@@ -27,8 +27,33 @@ def _vol(g, shape, dtype):
 @pytest.fixture(autouse=True)
 def _reset_precision():
     from paper_2203_10213_amd import vkt
+    rp = vkt.vktGetRowPairMinCells()
     yield
     vkt.vktSetPrecision("auto")
+    vkt.vktSetRowPairMinCells(rp)
+
+
+@pytest.mark.parametrize("precision", ["splitbf16", "splitbf16x6"])
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16, np.float32])
+@pytest.mark.parametrize("mode", ["clamp", "wrap", "border"])
+def test_row_pair_kernel_forced(orc, precision, dtype, mode):
+    """The row-pair kernel (k = 5, and 3-product float32 k = 7) on small,
+    ragged volumes: the row-pair threshold at 0 cells sends every such job
+    there; the other jobs keep their 16x16x32 path."""
+    from paper_2203_10213_amd import vkt
+    vkt.vktSetRowPairMinCells(0)
+    g = np.random.default_rng(350 + MODES.index(mode))
+    for shape in SHAPES:
+        for k in (5, 7):
+            src = _vol(g, shape, dtype)
+            w = g.standard_normal((k, k, k)).astype(np.float32)
+            if dtype != np.float32:
+                w = np.abs(w) / np.abs(w).sum()
+            out = run_filter(src, w, mode, precision=precision)
+            check_against_oracle(orc, src, w, mode, out,
+                                 tol=1e-6 if (precision == "splitbf16x6"
+                                              and dtype == np.float32) else 1e-5,
+                                 what=f"row pairs {precision} {shape} k={k}")
 
 
 @pytest.mark.parametrize("precision", ["splitbf16", "splitbf16x6"])

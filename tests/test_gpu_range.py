@@ -42,18 +42,33 @@ CASES = [
     (np.uint16, (7, 35, 66), 5, "float", "fp32"),           # VALU FP32, integer cells
     (np.uint8, (8, 33, 264), 3, "int_u", "auto"),           # dot4 when the region is 4-aligned
     (np.uint8, (6, 20, 67), 5, "int_s", "auto"),            # VALU exact integer (odd rows)
-    (np.float32, (12, 70, 40), 7, "float", "auto"),         # MFMA row pairs bf16 x6
+    (np.float32, (12, 70, 40), 7, "float", "auto"),         # MFMA 16x16 bf16 x6
     (np.uint16, (20, 33, 37), 9, "float", "auto"),          # MFMA 32x32 fp16
-    (np.float32, (10, 131, 70), 7, "float", "splitbf16"),   # MFMA row pairs bf16 x3, 3 tile rows
-    (np.uint8, (9, 70, 45), 5, "float", "auto"),            # MFMA row pairs fp16, k = 5
-    (np.uint16, (8, 67, 99), 7, "float", "auto"),           # MFMA row pairs fp16 x4
+    (np.float32, (10, 131, 70), 7, "float", "splitbf16"),   # MFMA 16x16 bf16 x3
+    (np.uint8, (9, 70, 45), 5, "float", "auto"),            # MFMA 16x16 fp16, k = 5
+    (np.uint16, (8, 67, 99), 7, "float", "auto"),           # MFMA 16x16 fp16 x4
+    # the row-pair kernel, forced for these small regions (threshold 0):
+    (np.float32, (10, 131, 70), 7, "float", "splitbf16", "rp"),  # bf16 x3, 3 tile rows
+    (np.uint8, (9, 70, 45), 5, "float", "auto", "rp"),           # fp16, k = 5
+    (np.float32, (11, 66, 37), 5, "float", "auto", "rp"),        # bf16 x6, k = 5
 ]
 
 
 @pytest.mark.parametrize("mode", ["clamp", "mirror", "border", "wrap"])
 @pytest.mark.parametrize("case", range(len(CASES)))
 def test_range_matches_oracle_inside_and_keeps_outside(orc, mode, case):
-    dtype, shape, k, kind, precision = CASES[case]
+    from paper_2203_10213_amd import vkt
+    dtype, shape, k, kind, precision = CASES[case][:5]
+    rp = vkt.vktGetRowPairMinCells()
+    if CASES[case][5:] == ("rp",):
+        vkt.vktSetRowPairMinCells(0)
+    try:
+        _range_case(orc, mode, case, dtype, shape, k, kind, precision)
+    finally:
+        vkt.vktSetRowPairMinCells(rp)
+
+
+def _range_case(orc, mode, case, dtype, shape, k, kind, precision):
     g = np.random.default_rng(900 + 7 * case + len(mode))
     if dtype == np.float32:
         src = g.standard_normal(shape).astype(np.float32)
