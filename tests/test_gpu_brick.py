@@ -139,7 +139,7 @@ def test_invalid_arguments():
             vkt.vktStructuredVolumeDestroy(h)
 
 
-def test_bench_workload_bricks(orc):
+def test_512_uint8_into_64_bricks_with_2_ghosts(orc):
     """The 512^3 uint8 phantom into 64^3 bricks with 2 ghost cells under
     clamp (512 bricks, one launch), every brick bit-exact."""
     from paper_2203_10213_amd import synth, vkt
