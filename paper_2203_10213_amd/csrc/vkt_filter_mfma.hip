@@ -74,13 +74,14 @@ struct Cfg {
     // (32x32 tiles: one row block where that brings the kernel down to two
     // waves per SIMD -- 9^3 with uint8 or 3-product float32 operands, 21 %
     // faster on the 1024^3 9^3 workload, and, with the accumulators in
-    // VGPRs, uint16 9^3 and k >= 11 except 6-product float32: 2048x2048x1024
-    // 11^3 uint16 71.5 -> 53.9 ms, 512^3 k = 11 / 13 / 15 uint8 1.78 / 1.70 /
-    // 1.92 -> 1.34 / 1.35 / 1.67 ms, 512^3 9^3 uint16 2.30 -> 2.02 ms;
-    // elsewhere it stays at one wave and the taller tile measured faster)
-    static constexpr int SY_DEFAULT =
-        SHAPE == 16 ? 2
-                    : ((K == 9 && PM != kF32x6) || (K >= 11 && PM != kF32x6) ? 1 : 2);
+    // VGPRs, every k >= 9 except 6-product float32 with k >= 13:
+    // 2048x2048x1024 11^3 uint16 71.5 -> 53.9 ms, 512^3 k = 11 / 13 / 15
+    // uint8 1.78 / 1.70 / 1.92 -> 1.34 / 1.35 / 1.67 ms, 512^3 9^3 uint16
+    // 2.30 -> 2.02 ms, 1024^3 9^3 six products 22.7 -> 20.6 ms; 6-product
+    // 13^3 and 15^3 would spill 37 and 61 registers there and keep the taller
+    // tile at one wave)
+    static constexpr bool ONE_BLOCK = SHAPE == 32 && (PM != kF32x6 || K <= 11);
+    static constexpr int SY_DEFAULT = SHAPE == 16 ? 2 : (ONE_BLOCK ? 1 : 2);
     static constexpr int SY = SYV ? SYV : SY_DEFAULT;
     static constexpr int TX = SX * NX, TY = SY * M::MT;             // 32 x 32 or 32 x 64 tile
     // a lane's 8-column windows of the wave's WS strips span SEGN columns,
@@ -97,10 +98,11 @@ struct Cfg {
     // with uint8 or 3-product float32 operands fit 128 registers (four
     // waves) without spills; uint16 and 6-product float32 would spill there
     // and keep three; 32x32 tiles take what they need (one or two), except
-    // the one-block k >= 9 kernels, held to two waves (198-254 registers;
-    // 15^3 uint16 spills 14, and measured no slower)
+    // the one-block kernels, held to two waves (196-256 registers; 15^3
+    // uint16 and 11^3 six-product float32 spill 14 and 15, and measured
+    // faster or no slower)
     static constexpr int WAVES =
-        SHAPE == 16 ? (PM == kU8 || PM == kF32x3 ? 4 : 3) : (K >= 9 && PM != kF32x6 ? 2 : 1);
+        SHAPE == 16 ? (PM == kU8 || PM == kF32x3 ? 4 : 3) : (ONE_BLOCK ? 2 : 1);
     // the persistent batched kernels need more registers: three waves for
     // the 16-bit operand classes, the float32 classes as they come
     static constexpr int BWAVES = SHAPE == 16 && (PM == kU8 || PM == kU16) ? 3 : 1;
