@@ -81,6 +81,14 @@ struct Cfg {
     // 13^3 and 15^3 would spill 37 and 61 registers there and keep the taller
     // tile at one wave)
     static constexpr bool ONE_BLOCK = SHAPE == 32 && (PM != kF32x6 || K <= 11);
+    // segment reads of the next (row block, K chunk) group issued before the
+    // current group's products: on 16x16 tiles, for uint16 and for 3-product
+    // float32 9^3 (224 registers, no spills; 1024^3 12.45 -> 11.77 ms, 512^3
+    // 1.66 -> 1.58 ms, bit-identical).  The other 32x32 kernels read each
+    // group's segments just before its products: uint8 9^3 / 11^3 measured 1 %
+    // slower pipelined, float32 11^3 the same, and 6-product float32 spills.
+    static constexpr bool PIPE = SHAPE == 16 || std::is_same<T, uint16_t>::value ||
+                                 (std::is_same<T, float>::value && PM != kF32x6 && K <= 9);
     static constexpr int SY_DEFAULT = SHAPE == 16 ? 2 : (ONE_BLOCK ? 1 : 2);
     static constexpr int SY = SYV ? SYV : SY_DEFAULT;
     static constexpr int TX = SX * NX, TY = SY * M::MT;             // 32 x 32 or 32 x 64 tile
@@ -267,8 +275,8 @@ __device__ void mfma_tile(const VolDesc& a, const float* __restrict__ w, int til
         const int cur = (zi - zi_beg) & 1;
         gather(min(zi + 1, zi_end - 1));
 
-        // (row block, K chunk) groups, software pipelined: the LDS segments
-        // of group g + 1 are read while group g's products issue
+        // (row block, K chunk) groups, software pipelined where C::PIPE: the
+        // LDS segments of group g + 1 are read while group g's products issue
         constexpr int NG = C::SY * C::NCH;
         u32x4 seg[2][PC::PS][C::NRD];
         auto load_seg = [&](int g, u32x4 (&sg)[PC::PS][C::NRD]) {
@@ -284,9 +292,7 @@ __device__ void mfma_tile(const VolDesc& a, const float* __restrict__ w, int til
                     sg[ps][h] = *reinterpret_cast<const u32x4*>(
                         &lds[cur][ps][row * C::PITCH + acol + 8 * h]);
         };
-        // (float32 volumes on 32x32 tiles, short of registers, read each
-        // group's segments just before its products: measured faster there)
-        constexpr bool PIPE = C::SHAPE == 16 || std::is_same<T, uint16_t>::value;
+        constexpr bool PIPE = C::PIPE;
         // the products at raised wave priority (the issue arbiter prefers
         // this wave's matrix work over other waves' staging and epilogues)
         __builtin_amdgcn_s_setprio(1);
